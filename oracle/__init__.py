@@ -1,0 +1,240 @@
+"""Oracle for the skew-symmetric SpMV path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct host implementations of every step of the
+path (validation, reverse Cuthill-McKee with fixed tie-breaking, the
+sign-fixing symmetric permutation, the three-way band split, full-CSR and
+serial SSS products, precision rounding, MRS, sparsity features; the MLP lives
+in ``oracle.mlp``).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may use it.  It shares no code with the
+library under ``paper_2407_17651_amd`` and never imports it.
+
+Matrices are passed as any object with ``n``, ``rowptr`` (int32[n+1]),
+``col`` (int32[nnz]) and ``val`` (float64[nnz]) holding the strictly lower
+triangle L of S = L - L^T.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from types import SimpleNamespace
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared"]
+
+
+def build(force: bool = False) -> str:
+    """Compile ``liboracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i32, i64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "or_validate": ([i64, i64, _vp, _vp], ctypes.c_int),
+            "or_rcm": ([i32, _vp, _vp, _vp], ctypes.c_int),
+            "or_permute": ([i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "or_split": ([i32, _vp, _vp, i32, i32, _vp, _vp, _vp], ctypes.c_int),
+            "or_full_csr": ([i32, _vp, _vp, _vp, d, _vp, _vp, _vp], i64),
+            "or_csr_spmv": ([i32, _vp, _vp, _vp, _vp, _vp], None),
+            "or_sss_spmv": ([i32, _vp, _vp, _vp, d, _vp, _vp], None),
+            "or_round_f32": ([i64, _vp, _vp], None),
+            "or_round_bf16": ([i64, _vp, _vp], None),
+            "or_bf16_to_f64": ([i64, _vp, _vp], None),
+            "or_mrs": ([i32, _vp, _vp, _vp, d, _vp, _vp, d, i32, _vp, _vp], ctypes.c_int),
+            "or_features": ([i32, _vp, _vp, _vp], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+def _arrs(L):
+    return (int(L.n), np.ascontiguousarray(L.rowptr, np.int32), np.ascontiguousarray(L.col, np.int32),
+            np.ascontiguousarray(L.val, np.float64))
+
+
+def validate(n, nnz, rowptr, col) -> int:
+    """0 ok, 1 malformed sizes/row pointers, 2 entry not strictly lower,
+    3 unsorted or duplicate columns."""
+    rp = None if rowptr is None else np.ascontiguousarray(rowptr, np.int32)
+    c = None if col is None else np.ascontiguousarray(col, np.int32)
+    if rp is not None and rp.shape[0] < max(n, 0) + 1:
+        return 1
+    if c is not None and nnz > 0 and c.shape[0] < nnz:
+        return 1
+    return int(_L().or_validate(n, nnz, _p(rp), _p(c)))
+
+
+def rcm(L) -> np.ndarray:
+    """Reverse Cuthill-McKee permutation: new position k holds old node perm[k]."""
+    n, rp, c, _ = _arrs(L)
+    perm = np.zeros(max(n, 0), np.int32)
+    if n > 0 and _L().or_rcm(n, _p(rp), _p(c), _p(perm)) != 0:
+        raise MemoryError("or_rcm")
+    return perm
+
+
+def permute(L, perm) -> SimpleNamespace:
+    """Strictly lower triangle of P S P^T (sign rule of eq. (2)), rows sorted."""
+    n, rp, c, v = _arrs(L)
+    perm = np.ascontiguousarray(perm, np.int32)
+    nnz = c.shape[0]
+    orow = np.zeros(n + 1, np.int32)
+    ocol = np.zeros(nnz, np.int32)
+    oval = np.zeros(nnz, np.float64)
+    if n > 0 and _L().or_permute(n, _p(rp), _p(c), _p(v), _p(perm), _p(orow), _p(ocol), _p(oval)) != 0:
+        raise MemoryError("or_permute")
+    return SimpleNamespace(n=n, rowptr=orow, col=ocol, val=oval, nnz=int(nnz))
+
+
+def split(L, w_in: int = -1, t_out: int = -1):
+    """Three-way split: (part int8[nnz], counts int64[3], (w_in, t_out, beta))."""
+    n, rp, c, _ = _arrs(L)
+    part = np.zeros(c.shape[0], np.int8)
+    cnt = np.zeros(3, np.int64)
+    params = np.zeros(3, np.int32)
+    if _L().or_split(n, _p(rp), _p(c), w_in, t_out, _p(part), cnt.ctypes.data, params.ctypes.data) != 0:
+        raise ValueError("w_in > t_out")
+    return part, cnt, tuple(int(t) for t in params)
+
+
+def full_csr(L, alpha: float = 0.0):
+    """Full CSR (frow, fcol, fval) of alpha*I + S, columns ascending."""
+    n, rp, c, v = _arrs(L)
+    cap = 2 * c.shape[0] + n
+    frow = np.zeros(n + 1, np.int32)
+    fcol = np.zeros(max(cap, 1), np.int32)
+    fval = np.zeros(max(cap, 1), np.float64)
+    m = _L().or_full_csr(n, _p(rp), _p(c), _p(v), float(alpha), _p(frow), _p(fcol), _p(fval))
+    if m < 0:
+        raise MemoryError("or_full_csr")
+    return frow, fcol[:m].copy(), fval[:m].copy()
+
+
+def csr_spmv(frow, fcol, fval, x) -> np.ndarray:
+    n = frow.shape[0] - 1
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros(n, np.float64)
+    if n > 0:
+        _L().or_csr_spmv(n, _p(frow), _p(fcol), _p(fval), _p(x), _p(y))
+    return y
+
+
+def spmv(L, alpha: float, x) -> np.ndarray:
+    """y = (alpha*I + S) x by the full-CSR definition; x may be n or n x k."""
+    x = np.asarray(x, np.float64)
+    frow, fcol, fval = full_csr(L, alpha)
+    if x.ndim == 1:
+        return csr_spmv(frow, fcol, fval, x)
+    return np.stack([csr_spmv(frow, fcol, fval, np.ascontiguousarray(x[:, j])) for j in range(x.shape[1])], 1)
+
+
+def sss_spmv(L, alpha: float, x) -> np.ndarray:
+    """Serial SSS skew product (the paper's baseline kernel semantics)."""
+    n, rp, c, v = _arrs(L)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros(n, np.float64)
+    if n > 0:
+        _L().or_sss_spmv(n, _p(rp), _p(c), _p(v), float(alpha), _p(x), _p(y))
+    return y
+
+
+def round_f32(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, np.float64)
+    out = np.zeros(a.shape, np.float32)
+    if a.size:
+        _L().or_round_f32(a.size, _p(a), _p(out))
+    return out
+
+
+def round_bf16(a) -> np.ndarray:
+    """FP32 -> BF16 bits (uint16), round to nearest even."""
+    a = np.ascontiguousarray(a, np.float32)
+    out = np.zeros(a.shape, np.uint16)
+    if a.size:
+        _L().or_round_bf16(a.size, _p(a), _p(out))
+    return out
+
+
+def bf16_to_f64(b) -> np.ndarray:
+    b = np.ascontiguousarray(b, np.uint16)
+    out = np.zeros(b.shape, np.float64)
+    if b.size:
+        _L().or_bf16_to_f64(b.size, _p(b), _p(out))
+    return out
+
+
+def rounded_values(val, dtype: str) -> np.ndarray:
+    """Stored values after the precision conversion, as float64."""
+    if dtype == "f64":
+        return np.asarray(val, np.float64).copy()
+    f = round_f32(val)
+    if dtype == "f32":
+        return f.astype(np.float64)
+    if dtype == "bf16":
+        return bf16_to_f64(round_bf16(f))
+    raise ValueError(dtype)
+
+
+def mrs(L, alpha: float, b, x0=None, tol: float = 1e-10, maxit: int = 1000):
+    """MRS for (alpha*I + S) x = b.  Returns (x, info, hist) with info keys
+    iters, status (0 converged / 1 maxit / 2 breakdown), eta, relres."""
+    n, rp, c, v = _arrs(L)
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.zeros(n, np.float64) if x0 is None else np.array(x0, np.float64, copy=True)
+    hist = np.zeros(max(maxit, 1), np.float64)
+    info = np.zeros(4, np.float64)
+    if _L().or_mrs(n, _p(rp), _p(c), _p(v), float(alpha), _p(b), _p(x), float(tol), int(maxit), _p(hist),
+                   info.ctypes.data) != 0:
+        raise MemoryError("or_mrs")
+    it = int(info[0])
+    return x, {"iters": it, "status": int(info[1]), "eta": float(info[2]), "relres": float(info[3])}, hist[:it].copy()
+
+
+def residual(L, alpha: float, b, x) -> float:
+    """||b - (alpha*I + S) x||_2 / ||b||_2 by the full-CSR definition."""
+    r = np.asarray(b, np.float64) - spmv(L, alpha, x)
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(r)) / (nb if nb > 0 else 1.0)
+
+
+def features(L) -> np.ndarray:
+    n, rp, c, _ = _arrs(L)
+    f = np.zeros(32, np.float64)
+    if _L().or_features(n, _p(rp), _p(c), f.ctypes.data) != 0:
+        raise MemoryError("or_features")
+    return f
+
+
+def bandwidth(L) -> int:
+    """max(i - j) over stored entries (0 when empty)."""
+    n, rp, c, _ = _arrs(L)
+    if c.size == 0:
+        return 0
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    return int((rows - c).max())

@@ -1,0 +1,568 @@
+/*
+ * Oracle for the skew-symmetric SpMV path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow, single-threaded host C that states
+ * what the path computes.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg load it; the library never does, and it shares no code,
+ * header or constant with the GPU path.  Built with -O2 -fno-fast-math
+ * -ffp-contract=off so that every product and sum is rounded as written.
+ *
+ * Conventions.  The input is the strictly lower triangle L of a skew-symmetric
+ * S (S = -S^T, zero diagonal) in CSR: rowptr[n+1], col[nnz], val[nnz].  The
+ * stored entry l_ij (i > j) stands for S_ij = l_ij and S_ji = -l_ij (the
+ * symmetric-pair rule of eqs. (2)-(6), Section 3.1.2).  The system matrix is
+ * A = alpha*I + S (shifted skew-symmetric form, Section 1).
+ *
+ * Parity notes: every function here is pinned by the CPU tests against
+ * closed forms, dense products, brute force or hand-derived cases.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Input validation (storage of one triangle, Sections 1 and 3).
+ * Returns 0 when (rowptr, col) is a strictly lower CSR with strictly
+ * increasing columns in every row; 1 for malformed sizes or row pointers;
+ * 2 for an entry outside the strictly lower triangle; 3 for unsorted or
+ * duplicate columns.  Rows are checked in order, entries in order; the first
+ * violation decides the code. */
+int or_validate(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col) {
+  if (n < 0 || nnz < 0 || n > 0x7fffffffLL || nnz > 0x7fffffffLL) return 1;
+  if (!rowptr) return 1;
+  if (nnz > 0 && !col) return 1;
+  if (rowptr[0] != 0 || rowptr[n] != nnz) return 1;
+  for (int64_t i = 0; i < n; i++)
+    if (rowptr[i + 1] < rowptr[i]) return 1;
+  for (int64_t i = 0; i < n; i++) {
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      if (col[e] < 0 || col[e] >= i) return 2;
+      if (e > rowptr[i] && col[e] <= col[e - 1]) return 3;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Graph of S: N(v) = {j : (v,j) stored} U {i : (i,v) stored}. */
+typedef struct {
+  int32_t n;
+  int32_t *deg, *ptr, *adj;
+} graph;
+
+static int graph_build(int32_t n, const int32_t *rowptr, const int32_t *col, graph *g) {
+  g->n = n;
+  g->deg = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+  g->ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+  int64_t m = n > 0 ? rowptr[n] : 0;
+  g->adj = (int32_t *)malloc((size_t)(2 * m + 1) * sizeof(int32_t));
+  int32_t *fill = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+  if (!g->deg || !g->ptr || !g->adj || !fill) {
+    free(fill);
+    return 1;
+  }
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      g->deg[i]++;
+      g->deg[col[e]]++;
+    }
+  for (int32_t i = 0; i < n; i++) g->ptr[i + 1] = g->ptr[i] + g->deg[i];
+  for (int32_t i = 0; i < n; i++) fill[i] = g->ptr[i];
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      int32_t j = col[e];
+      g->adj[fill[i]++] = j;
+      g->adj[fill[j]++] = i;
+    }
+  free(fill);
+  return 0;
+}
+static void graph_free(graph *g) {
+  free(g->deg);
+  free(g->ptr);
+  free(g->adj);
+}
+
+/* (deg, index) order used by every tie-break of the reordering. */
+static const int32_t *g_cmp_deg;
+static int less_deg_idx(int32_t a, int32_t b) {
+  return g_cmp_deg[a] < g_cmp_deg[b] || (g_cmp_deg[a] == g_cmp_deg[b] && a < b);
+}
+static int cmp_deg_idx(const void *pa, const void *pb) {
+  int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
+  if (a == b) return 0;
+  return less_deg_idx(a, b) ? -1 : 1;
+}
+
+/* Level structure of a BFS from s inside its component.  Returns the
+ * eccentricity (number of levels - 1) and the nodes of the last level in
+ * last[0..*nlast).  `stamp`/`id` mark visited nodes without clearing. */
+static int32_t bfs_levels(const graph *g, int32_t s, int32_t *queue, int32_t *stamp, int32_t id,
+                          int32_t *last, int32_t *nlast) {
+  int32_t head = 0, tail = 0;
+  queue[tail++] = s;
+  stamp[s] = id;
+  int32_t level = 0, level_start = 0, level_end = 1;
+  for (;;) {
+    while (head < level_end) {
+      int32_t v = queue[head++];
+      for (int32_t e = g->ptr[v]; e < g->ptr[v + 1]; e++) {
+        int32_t u = g->adj[e];
+        if (stamp[u] != id) {
+          stamp[u] = id;
+          queue[tail++] = u;
+        }
+      }
+    }
+    if (tail == level_end) break; /* no next level */
+    level++;
+    level_start = level_end;
+    level_end = tail;
+  }
+  *nlast = level_end - level_start;
+  memcpy(last, queue + level_start, (size_t)(*nlast) * sizeof(int32_t));
+  return level;
+}
+
+/* Reverse Cuthill-McKee with fixed tie-breaking (the reordering that turns
+ * the matrix into a band, Sections 1 and 3.1.2; Cuthill-McKee, Section 2).
+ *   (a) s = the unvisited node minimising (deg, index);
+ *   (b) George-Liu pseudo-peripheral search from s: build the BFS level
+ *       structure; take u of minimum (deg, index) in the last level; if u has
+ *       a larger eccentricity, move to u and repeat, else stop;
+ *   (c) Cuthill-McKee BFS from s: pop v, append v to the order, push the
+ *       unvisited neighbours of v in ascending (deg, index);
+ *   repeat (a)-(c) until every node is ordered; finally reverse the whole
+ *   concatenated order: perm[k] = order[n-1-k] (new position k holds old node
+ *   perm[k]).  Returns 0, or 1 when out of memory. */
+int or_rcm(int32_t n, const int32_t *rowptr, const int32_t *col, int32_t *perm) {
+  if (n <= 0) return 0;
+  graph g;
+  if (graph_build(n, rowptr, col, &g)) {
+    graph_free(&g);
+    return 1;
+  }
+  int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *byrank = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *stamp = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+  int32_t *last = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *nb = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  char *visited = (char *)calloc((size_t)n, 1);
+  if (!order || !byrank || !queue || !stamp || !last || !nb || !visited) {
+    free(order); free(byrank); free(queue); free(stamp); free(last); free(nb); free(visited);
+    graph_free(&g);
+    return 1;
+  }
+  g_cmp_deg = g.deg;
+  /* all nodes in ascending (deg, index): step (a) scans this list */
+  for (int32_t v = 0; v < n; v++) byrank[v] = v;
+  qsort(byrank, (size_t)n, sizeof(int32_t), cmp_deg_idx);
+
+  int32_t nord = 0, scan = 0, bfs_id = 0;
+  while (nord < n) {
+    /* (a) */
+    while (visited[byrank[scan]]) scan++;
+    int32_t s = byrank[scan];
+    /* (b) */
+    int32_t nlast;
+    int32_t ecc_s = bfs_levels(&g, s, queue, stamp, ++bfs_id, last, &nlast);
+    for (;;) {
+      int32_t u = last[0];
+      for (int32_t t = 1; t < nlast; t++)
+        if (less_deg_idx(last[t], u)) u = last[t];
+      if (u == s) break;
+      int32_t nlast_u;
+      int32_t ecc_u = bfs_levels(&g, u, queue, stamp, ++bfs_id, nb, &nlast_u);
+      if (ecc_u > ecc_s) {
+        s = u;
+        ecc_s = ecc_u;
+        nlast = nlast_u;
+        memcpy(last, nb, (size_t)nlast * sizeof(int32_t));
+      } else {
+        break;
+      }
+    }
+    /* (c): the order array doubles as the FIFO queue */
+    int32_t head = nord;
+    visited[s] = 1;
+    order[nord++] = s;
+    while (head < nord) {
+      int32_t v = order[head++];
+      int32_t k = 0;
+      for (int32_t e = g.ptr[v]; e < g.ptr[v + 1]; e++)
+        if (!visited[g.adj[e]]) nb[k++] = g.adj[e];
+      qsort(nb, (size_t)k, sizeof(int32_t), cmp_deg_idx);
+      for (int32_t t = 0; t < k; t++) {
+        visited[nb[t]] = 1;
+        order[nord++] = nb[t];
+      }
+    }
+  }
+  for (int32_t k = 0; k < n; k++) perm[k] = order[n - 1 - k];
+  free(order); free(byrank); free(queue); free(stamp); free(last); free(nb); free(visited);
+  graph_free(&g);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Symmetric permutation B = P A P^T, B[k,l] = S[perm[k], perm[l]], stored as
+ * its strictly lower triangle.  A stored l_ij (i > j) lands at
+ * (p, q) = (iperm[i], iperm[j]); if p > q it is stored as l_ij at (p, q),
+ * otherwise as -l_ij at (q, p), because S_ji = -S_ij (eq. (2)).  Rows are
+ * sorted by column.  Output arrays have n+1 and nnz entries. */
+typedef struct {
+  int32_t c;
+  double v;
+} cv_pair;
+static int cmp_cv(const void *a, const void *b) {
+  int32_t x = ((const cv_pair *)a)->c, y = ((const cv_pair *)b)->c;
+  return (x > y) - (x < y);
+}
+
+int or_permute(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+               const int32_t *perm, int32_t *orow, int32_t *ocol, double *oval) {
+  if (n < 0) return 1;
+  int32_t nnz = n > 0 ? rowptr[n] : 0;
+  int32_t *iperm = (int32_t *)malloc((size_t)(n + 1) * sizeof(int32_t));
+  int32_t *fill = (int32_t *)malloc((size_t)(n + 1) * sizeof(int32_t));
+  cv_pair *tmp = (cv_pair *)malloc((size_t)(nnz + 1) * sizeof(cv_pair));
+  if (!iperm || !fill || !tmp) {
+    free(iperm); free(fill); free(tmp);
+    return 1;
+  }
+  for (int32_t k = 0; k < n; k++) iperm[perm[k]] = k;
+  memset(orow, 0, (size_t)(n + 1) * sizeof(int32_t));
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      int32_t p = iperm[i], q = iperm[col[e]];
+      orow[(p > q ? p : q) + 1]++;
+    }
+  for (int32_t i = 0; i < n; i++) orow[i + 1] += orow[i];
+  for (int32_t i = 0; i < n; i++) fill[i] = orow[i];
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      int32_t p = iperm[i], q = iperm[col[e]];
+      if (p > q) {
+        tmp[fill[p]].c = q;
+        tmp[fill[p]++].v = val[e];
+      } else {
+        tmp[fill[q]].c = p;
+        tmp[fill[q]++].v = -val[e];
+      }
+    }
+  for (int32_t r = 0; r < n; r++) qsort(tmp + orow[r], (size_t)(orow[r + 1] - orow[r]), sizeof(cv_pair), cmp_cv);
+  for (int32_t e = 0; e < nnz; e++) {
+    ocol[e] = tmp[e].c;
+    oval[e] = tmp[e].v;
+  }
+  free(iperm); free(fill); free(tmp);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Three-way split of the band (Sections 1 and 3.1.2).  For a stored entry at
+ * distance d = i - j: inner if d <= w_in, middle if w_in < d <= t_out, outer if
+ * d > t_out.  beta = max d (0 when nnz = 0).  Negative parameters select the
+ * defaults: w_in = 0 (the "inner bandwidth of size 1" is the main diagonal,
+ * which for S is the shift alone) and t_out = max(beta - 3, 0) (the "outer
+ * bandwidth = 3" read as the three outermost diagonals).  part[e] is 0, 1 or
+ * 2; cnt[0..2] the part sizes; params[0..2] = (w_in, t_out, beta) as used.
+ * Returns 1 when w_in > t_out. */
+int or_split(int32_t n, const int32_t *rowptr, const int32_t *col, int32_t w_in, int32_t t_out,
+             int8_t *part, int64_t *cnt, int32_t *params) {
+  int32_t beta = 0;
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++)
+      if (i - col[e] > beta) beta = i - col[e];
+  if (w_in < 0) w_in = 0;
+  if (t_out < 0) t_out = beta - 3 > 0 ? beta - 3 : 0;
+  if (w_in > t_out) return 1;
+  cnt[0] = cnt[1] = cnt[2] = 0;
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      int32_t d = i - col[e];
+      int8_t p = d <= w_in ? 0 : (d <= t_out ? 1 : 2);
+      part[e] = p;
+      cnt[p]++;
+    }
+  params[0] = w_in;
+  params[1] = t_out;
+  params[2] = beta;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full CSR of A = alpha*I + S with ascending columns in every row: row i holds
+ * l_ij for stored (i, j), then alpha at (i, i) when alpha != 0, then -l_ki for
+ * every stored (k, i), k > i.  frow[n+1]; fcol/fval sized 2*nnz + n. */
+int64_t or_full_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                    double alpha, int32_t *frow, int32_t *fcol, double *fval) {
+  int32_t *cnt = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+  int32_t *fill = (int32_t *)malloc((size_t)(n + 1) * sizeof(int32_t));
+  if (!cnt || !fill) {
+    free(cnt); free(fill);
+    return -1;
+  }
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      cnt[i]++;
+      cnt[col[e]]++;
+    }
+  frow[0] = 0;
+  for (int32_t i = 0; i < n; i++) frow[i + 1] = frow[i] + cnt[i] + (alpha != 0.0 ? 1 : 0);
+  for (int32_t i = 0; i < n; i++) {
+    int32_t f = frow[i];
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      fcol[f] = col[e];
+      fval[f++] = val[e];
+    }
+    if (alpha != 0.0) {
+      fcol[f] = i;
+      fval[f++] = alpha;
+    }
+    fill[i] = f;
+  }
+  for (int32_t k = 0; k < n; k++)
+    for (int32_t e = rowptr[k]; e < rowptr[k + 1]; e++) {
+      int32_t i = col[e];
+      fcol[fill[i]] = k;
+      fval[fill[i]++] = -val[e];
+    }
+  int64_t total = frow[n];
+  free(cnt); free(fill);
+  return total;
+}
+
+/* y_i = sum_j a_ij x_j over row i in ascending column order. */
+void or_csr_spmv(int32_t n, const int32_t *frow, const int32_t *fcol, const double *fval,
+                 const double *x, double *y) {
+  for (int32_t i = 0; i < n; i++) {
+    double s = 0.0;
+    for (int32_t e = frow[i]; e < frow[i + 1]; e++) s += fval[e] * x[fcol[e]];
+    y[i] = s;
+  }
+}
+
+/* Serial SSS skew SpMV (the paper's baseline, Section 3.1.1, adapted to skew
+ * symmetry with the pair rule of eqs. (2)-(6)): y = alpha*x; then for every
+ * stored l = l_ij in row order: y_i += l * x_j and y_j -= l * x_i. */
+void or_sss_spmv(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                 double alpha, const double *x, double *y) {
+  for (int32_t i = 0; i < n; i++) y[i] = alpha * x[i];
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      int32_t j = col[e];
+      double l = val[e];
+      y[i] += l * x[j];
+      y[j] -= l * x[i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Precision rounding.  FP64 -> FP32: IEEE round to nearest even (the C
+ * conversion in the default rounding mode).  FP32 -> BF16: round to nearest
+ * even on the upper 16 bits; NaN becomes a quiet NaN with the same sign. */
+void or_round_f32(int64_t m, const double *in, float *out) {
+  for (int64_t i = 0; i < m; i++) out[i] = (float)in[i];
+}
+void or_round_bf16(int64_t m, const float *in, uint16_t *out) {
+  for (int64_t i = 0; i < m; i++) {
+    uint32_t u;
+    memcpy(&u, &in[i], 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      out[i] = (uint16_t)((u >> 16) | 0x0040u);
+    } else {
+      uint32_t lsb = (u >> 16) & 1u;
+      out[i] = (uint16_t)((u + 0x7fffu + lsb) >> 16);
+    }
+  }
+}
+void or_bf16_to_f64(int64_t m, const uint16_t *in, double *out) {
+  for (int64_t i = 0; i < m; i++) {
+    uint32_t u = (uint32_t)in[i] << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    out[i] = (double)f;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* MRS: minimal residual iteration for (alpha*I + S) x = b (Section 1 cites
+ * it: one product with S and one inner product per iteration).  x_k minimises
+ * ||b - A x|| over x_0 + K_k(S, r_0).  Skew Lanczos: w = S v_j + beta_j
+ * v_{j-1}, beta_{j+1} = ||w||, v_{j+1} = w / beta_{j+1}; then
+ * (alpha*I + S) V_k = V_{k+1} H_k with column j of H_k holding -beta_j in row
+ * j-1, alpha in row j and beta_{j+1} in row j+1.  H_k is reduced by Givens
+ * rotations as in MINRES (Paige and Saunders, 1975); |eta| is the residual
+ * norm of x_k.
+ *   info[0] = iterations, info[1] = status (0 converged, 1 maxit,
+ *   2 breakdown), info[2] = |eta|/||b||, info[3] = true ||b - A x||/||b||.
+ * hist (may be NULL) receives |eta_j| / ||b|| for j = 1..iterations. */
+static double dot(int32_t n, const double *a, const double *b) {
+  double s = 0.0;
+  for (int32_t i = 0; i < n; i++) s += a[i] * b[i];
+  return s;
+}
+
+int or_mrs(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, double alpha,
+           const double *b, double *x, double tol, int32_t maxit, double *hist, double *info) {
+  size_t sz = (size_t)(n > 0 ? n : 1) * sizeof(double);
+  double *r = (double *)malloc(sz), *v = (double *)malloc(sz), *vp = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double *w = (double *)malloc(sz), *p = (double *)malloc(sz);
+  double *p1 = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double *p2 = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  if (!r || !v || !vp || !w || !p || !p1 || !p2) {
+    free(r); free(v); free(vp); free(w); free(p); free(p1); free(p2);
+    return 1;
+  }
+  double bnorm = sqrt(dot(n, b, b));
+  int32_t it = 0, status = 1;
+  double eta = 0.0;
+  /* r0 = b - A x0 */
+  or_sss_spmv(n, rowptr, col, val, alpha, x, r);
+  for (int32_t i = 0; i < n; i++) r[i] = b[i] - r[i];
+  double beta1 = sqrt(dot(n, r, r));
+  if (bnorm == 0.0) bnorm = 1.0;
+  eta = beta1;
+  if (beta1 == 0.0 || beta1 <= tol * bnorm) {
+    status = 0;
+  } else {
+    for (int32_t i = 0; i < n; i++) v[i] = r[i] / beta1;
+    double beta_j = 0.0; /* coefficient of v_{j-1}; v_0 = 0 */
+    double c1 = 1.0, s1 = 0.0, c2 = 1.0, s2 = 0.0; /* G_{j-1}, G_{j-2} */
+    for (it = 1; it <= maxit; it++) {
+      or_sss_spmv(n, rowptr, col, val, 0.0, v, w);
+      for (int32_t i = 0; i < n; i++) w[i] += beta_j * vp[i];
+      double beta_n = sqrt(dot(n, w, w));
+      double eps = s2 * (-beta_j);
+      double dbar = c2 * (-beta_j);
+      double delta = c1 * dbar + s1 * alpha;
+      double gbar = -s1 * dbar + c1 * alpha;
+      double gamma = sqrt(gbar * gbar + beta_n * beta_n);
+      if (gamma == 0.0) {
+        status = 2;
+        break;
+      }
+      double c = gbar / gamma, s = beta_n / gamma;
+      for (int32_t i = 0; i < n; i++) p[i] = (v[i] - delta * p1[i] - eps * p2[i]) / gamma;
+      for (int32_t i = 0; i < n; i++) x[i] += (c * eta) * p[i];
+      eta = -s * eta;
+      if (hist) hist[it - 1] = fabs(eta) / bnorm;
+      c2 = c1; s2 = s1; c1 = c; s1 = s;
+      double *t = p2; p2 = p1; p1 = p; p = t;
+      if (fabs(eta) <= tol * bnorm || beta_n == 0.0) {
+        status = 0;
+        break;
+      }
+      for (int32_t i = 0; i < n; i++) {
+        vp[i] = v[i];
+        v[i] = w[i] / beta_n;
+      }
+      beta_j = beta_n;
+    }
+    if (it > maxit) it = maxit;
+  }
+  /* true residual */
+  or_sss_spmv(n, rowptr, col, val, alpha, x, r);
+  for (int32_t i = 0; i < n; i++) r[i] = b[i] - r[i];
+  if (info) {
+    info[0] = (double)it;
+    info[1] = (double)status;
+    info[2] = fabs(eta) / bnorm;
+    info[3] = sqrt(dot(n, r, r)) / bnorm;
+  }
+  free(r); free(v); free(vp); free(w); free(p); free(p1); free(p2);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 32 sparsity features of a lower CSR (the band's bandwidth and density
+ * characteristics that Section 3.1.2 suggests for choosing the outer split).
+ * Row lower bandwidth b_i = i - min col(i) (0 for an empty row); d = i - j per
+ * entry; beta = max d; row length l_i.  Quantiles are nearest-rank on the
+ * sorted b_i (rank ceil(p n), 1-based).  Ratios with a zero denominator are 0.
+ *  f0  log2 n              f1  log2 nnz          f2  nnz / n
+ *  f3  beta / n            f4  log2(beta + 1)
+ *  f5..f9   b quantiles p10, p50, p90, p99, max, each / beta
+ *  f10 nnz / sum b_i (envelope fill)
+ *  f11..f18 fraction of entries with d <= 1, 2, 4, ..., 128
+ *  f19..f21 fraction with d/beta > 1/2, 3/4, 9/10
+ *  f22..f28 fraction of rows with length 0, 1, 2, 3-4, 5-8, 9-16, >= 17
+ *  f29 max l / mean l      f30 std(l) / mean(l) (population)
+ *  f31 fraction of 256-row tiles whose window r0 + 256 - lo_t (lo_t = the
+ *      smallest column in the tile, r0 + 256 clipped to n) fits 160 KiB of
+ *      FP64 x and y (16 bytes per row). */
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+int or_features(int32_t n, const int32_t *rowptr, const int32_t *col, double *f) {
+  for (int k = 0; k < 32; k++) f[k] = 0.0;
+  if (n <= 0) return 0;
+  int64_t nnz = rowptr[n];
+  int32_t *bw = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  if (!bw) return 1;
+  int64_t beta = 0, sumb = 0, maxl = 0, s1 = 0, s2 = 0;
+  int64_t dle[8] = {0}, dfar[3] = {0}, lenh[7] = {0};
+  for (int32_t i = 0; i < n; i++) {
+    int64_t l = rowptr[i + 1] - rowptr[i];
+    bw[i] = l > 0 ? i - col[rowptr[i]] : 0;
+    sumb += bw[i];
+    if (l > maxl) maxl = l;
+    s1 += l;
+    s2 += l * l;
+    int h = l == 0 ? 0 : l == 1 ? 1 : l == 2 ? 2 : l <= 4 ? 3 : l <= 8 ? 4 : l <= 16 ? 5 : 6;
+    lenh[h]++;
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      int64_t d = i - col[e];
+      if (d > beta) beta = d;
+    }
+  }
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      int64_t d = i - col[e];
+      for (int k = 0; k < 8; k++)
+        if (d <= (1 << k)) dle[k]++;
+      if (2 * d > beta) dfar[0]++;
+      if (4 * d > 3 * beta) dfar[1]++;
+      if (10 * d > 9 * beta) dfar[2]++;
+    }
+  qsort(bw, (size_t)n, sizeof(int32_t), cmp_i32);
+  f[0] = log2((double)n);
+  f[1] = nnz > 0 ? log2((double)nnz) : 0.0;
+  f[2] = (double)nnz / (double)n;
+  f[3] = (double)beta / (double)n;
+  f[4] = log2((double)(beta + 1));
+  if (beta > 0) {
+    static const int64_t pct[4] = {10, 50, 90, 99};
+    for (int k = 0; k < 4; k++) {
+      int64_t rank = (pct[k] * (int64_t)n + 99) / 100;
+      f[5 + k] = (double)bw[rank - 1] / (double)beta;
+    }
+    f[9] = (double)bw[n - 1] / (double)beta;
+  }
+  f[10] = sumb > 0 ? (double)nnz / (double)sumb : 0.0;
+  if (nnz > 0) {
+    for (int k = 0; k < 8; k++) f[11 + k] = (double)dle[k] / (double)nnz;
+    for (int k = 0; k < 3; k++) f[19 + k] = (double)dfar[k] / (double)nnz;
+  }
+  for (int k = 0; k < 7; k++) f[22 + k] = (double)lenh[k] / (double)n;
+  if (s1 > 0) {
+    f[29] = (double)(maxl * (int64_t)n) / (double)s1;
+    f[30] = sqrt((double)((int64_t)n * s2 - s1 * s1)) / (double)s1;
+  }
+  int64_t tiles = (n + 255) / 256, fit = 0;
+  for (int64_t t = 0; t < tiles; t++) {
+    int64_t r0 = t * 256, r1 = r0 + 256 < n ? r0 + 256 : n;
+    int64_t lo = r0;
+    for (int64_t i = r0; i < r1; i++)
+      if (rowptr[i + 1] > rowptr[i] && col[rowptr[i]] < lo) lo = col[rowptr[i]];
+    if ((r1 - lo) * 16 <= 160 * 1024) fit++;
+  }
+  f[31] = (double)fit / (double)tiles;
+  free(bw);
+  return 0;
+}
