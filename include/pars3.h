@@ -1,0 +1,168 @@
+/*
+ * pars3.h -- C ABI of the MI355X (gfx950) skew-symmetric SpMV library.
+ *
+ * Problem (Section 1, eq. (1)): products and solves with a sparse
+ * skew-symmetric S (S = -S^T) or a shifted skew-symmetric A = alpha*I + S.
+ * Only the strictly lower triangle L of S is stored (the SSS idea of keeping
+ * one triangle, Sections 1 and 3), so S = L - L^T and every stored l_ij
+ * (i > j) contributes y_i += l_ij x_j and y_j -= l_ij x_i (eqs. (2)-(6),
+ * Section 3.1.2).  Before multiplying, the matrix is reordered by reverse
+ * Cuthill-McKee into a band and the band is split three ways (diagonal/inner,
+ * middle, outer) by distance from the diagonal (Sections 1 and 3.1.2).
+ *
+ * Conventions for every call:
+ *  - Return value: pars3_status; PARS3_OK (0) on success.  On failure a
+ *    message is available from pars3_last_error() (thread-local).
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *    device memory (for example torch tensors' data_ptr()).  The library never
+ *    takes ownership of caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it; calls documented as synchronous wait for
+ *    it before returning.
+ *  - Device faults of asynchronous calls surface as PARS3_EHIP at the next
+ *    synchronising call.
+ *  - One handle must not be used from two threads at once; distinct handles
+ *    are independent.  No C++ exception crosses this interface.
+ */
+#ifndef PARS3_H
+#define PARS3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PARS3_OK = 0,
+  PARS3_EINVAL = 1,     /* invalid argument, sizes or row pointers */
+  PARS3_ENOTLOWER = 2,  /* an entry outside the strictly lower triangle */
+  PARS3_EUNSORTED = 3,  /* unsorted or duplicate columns in a row */
+  PARS3_ENOMEM = 4,     /* host or device allocation failed */
+  PARS3_EHIP = 5,       /* HIP runtime error */
+  PARS3_ESTATE = 6,     /* wrong call order or dtype not available */
+  PARS3_ENOCONV = 7,    /* iteration limit reached before the tolerance */
+  PARS3_EBREAKDOWN = 8, /* singular recurrence (gamma = 0) */
+  PARS3_ENAN = 9,       /* NaN or Inf met in a solver */
+  PARS3_EIO = 10        /* file input/output error */
+} pars3_status;
+
+typedef enum { PARS3_F64 = 0, PARS3_F32 = 1, PARS3_BF16 = 2 } pars3_dtype;
+
+enum { PARS3_ORDER_RCM = 0, PARS3_ORDER_ORIGINAL = 1 };
+
+enum { PARS3_Y_AUTO = 0, PARS3_Y_WINDOW = 1, PARS3_Y_ATOMIC = 2 };
+
+typedef struct pars3_matrix pars3_matrix;
+
+/* Split and layout parameters of pars3_reorder (Sections 1 and 3.1.2: the
+ * band is split into an inner part, a middle part and an outer part whose
+ * distance from the diagonal is a user-given bandwidth).  For a stored entry at
+ * distance d = i - j (in the reordered matrix):
+ *   inner  : d <= w_in            (w_in = 0: only the diagonal, i.e. the shift)
+ *   middle : w_in < d <= t_out
+ *   outer  : d > t_out
+ * Fields set to -1 (or 0 where noted) take the defaults. */
+typedef struct {
+  int32_t w_in;        /* inner half-width >= 0; -1 = 0 (the paper's diagonal split) */
+  int32_t t_out;       /* middle/outer boundary; -1 = max(beta - 3, 0) ("outer bandwidth 3") */
+  int32_t tile_rows;   /* rows per tile: 64, 128, 256, 512 or 1024; 0 = 256 */
+  int32_t window_max;  /* max length of a tile's back window of columns; 0 = 1024 */
+  int32_t y_mode;      /* PARS3_Y_AUTO/WINDOW: LDS windows where they fit; PARS3_Y_ATOMIC: none */
+  int32_t value_dtype; /* pars3_dtype of the stored values used by pars3_spmv */
+  int32_t keep_fp64;   /* also keep FP64 values (needed by the mixed-precision solver) */
+  int32_t permute;     /* 1 = reverse Cuthill-McKee (default); 0 = keep the given order */
+} pars3_split_params;
+
+/* Fills `p` with the defaults (RCM, paper split, 256-row tiles, FP64). */
+void pars3_split_params_default(pars3_split_params *p);
+
+/* Read-back of the split (pars3_get_split_info). */
+typedef struct {
+  int64_t n, nnz;
+  int32_t beta;        /* max d after reordering (the RCM bandwidth) */
+  int32_t w_in, t_out; /* resolved split parameters */
+  int32_t tile_rows, window_max, y_mode, value_dtype, permute;
+  int64_t nnz_inner, nnz_middle, nnz_outer; /* the three parts, by definition */
+  int32_t n_tiles;
+  int32_t n_window_tiles;   /* tiles whose back window is held in LDS */
+  int64_t nnz_tiled;        /* entries processed by the tile kernel */
+  int64_t nnz_far;          /* entries processed by the coordinate kernel */
+  int32_t n_components;     /* connected components of the graph of S */
+  int32_t bfs_levels;       /* levels of the Cuthill-McKee search (max over components) */
+} pars3_split_info;
+
+/* Host-only validation of a strictly lower CSR (no device use).  Checks, rows
+ * in order and entries in order, the first violation deciding the code:
+ * EINVAL for n < 0, nnz < 0, n or nnz > INT32_MAX, NULL rowptr (or col when
+ * nnz > 0), rowptr[0] != 0, rowptr[n] != nnz, decreasing row pointers;
+ * ENOTLOWER for col < 0 or col >= row; EUNSORTED for a column not larger than
+ * its predecessor in the row (unsorted or duplicate). */
+pars3_status pars3_validate(int64_t n, int64_t nnz_lower, const int32_t *rowptr, const int32_t *col);
+
+/* Creates a handle from host arrays rowptr[n+1], col[nnz], val[nnz] holding
+ * the strictly lower triangle L (Sections 1 and 3: one triangle stored).  The
+ * arrays are validated (as pars3_validate) and copied to the current HIP
+ * device; the caller keeps ownership and may free them on return.  Explicit
+ * zeros are kept as structural entries.  n = 0 and nnz = 0 are valid.  On error
+ * *out is set to NULL and nothing stays allocated.  Synchronous. */
+pars3_status pars3_create(int64_t n, int64_t nnz_lower, const int32_t *rowptr, const int32_t *col,
+                          const double *val, pars3_matrix **out);
+
+/* Frees every device and host resource of the handle.  NULL is allowed. */
+void pars3_destroy(pars3_matrix *A);
+
+/* Reorders and splits on the GPU (Section 3.1.2: reverse Cuthill-McKee, then
+ * the three-way split; both are integer work and bit-exact against the fixed
+ * tie-break definition).  p == NULL selects the defaults.  Reverse
+ * Cuthill-McKee runs once per handle; later calls with other parameters only
+ * re-split and rebuild the layouts.  Synchronous (reads back the split sizes).
+ * Errors: EINVAL for out-of-range parameters or w_in > t_out. */
+pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *p, void *stream);
+
+/* y = shift*x + S*x  (the shifted skew-symmetric product; Section 1 and eqs.
+ * (2)-(6)).  x and y are device arrays of n x k values, row-major (k values of
+ * one row are contiguous), k in {1, 2, 4, 8}.  vec_dtype is PARS3_F64 when the
+ * stored values are FP64 and PARS3_F32 when they are FP32 or BF16 (FP32
+ * accumulation).  order = PARS3_ORDER_RCM: x and y are in the reordered
+ * numbering; PARS3_ORDER_ORIGINAL: in the caller's numbering (a gather and a
+ * scatter are added).  x and y must not overlap.  Asynchronous.  Errors:
+ * ESTATE before pars3_reorder or for a dtype mismatch; EINVAL otherwise. */
+pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x, void *y, int32_t k, int32_t vec_dtype,
+                        int32_t order, void *stream);
+
+/* Inspection (host output buffers, caller-allocated; synchronous).
+ * perm[n]: new position k holds old node perm[k].  The permuted strictly lower
+ * triangle is returned in CSR order (rows, then columns ascending):
+ * rowptr[n+1], col[nnz], val[nnz] (FP64, signs fixed by eq. (2)) and part[nnz]
+ * (0 inner, 1 middle, 2 outer); any output pointer may be NULL.  Values of the
+ * stored precision (pars3_get_values): FP64 as double, FP32 as float, BF16 as
+ * uint16 bit patterns, in the same CSR order. */
+pars3_status pars3_get_perm(const pars3_matrix *A, int32_t *perm);
+pars3_status pars3_get_permuted_lower(const pars3_matrix *A, int32_t *rowptr, int32_t *col, double *val,
+                                      int8_t *part);
+pars3_status pars3_get_split_info(const pars3_matrix *A, pars3_split_info *info);
+pars3_status pars3_get_values(const pars3_matrix *A, int32_t dtype, void *host);
+
+/* Per-kernel timing of products (measurement harness).  While enabled, every
+ * kernel that pars3_spmv launches is bracketed by two hipEvents recorded on the
+ * launch stream (at most 4096 products between reads; later ones are not
+ * timed).  pars3_get_profile waits for the recorded events, returns the summed
+ * durations in milliseconds per kernel class (inner-band/initialisation, tile,
+ * coordinate-list) and the number of timed products, then resets the
+ * counters. */
+typedef struct {
+  int64_t calls;
+  double ms_inner, ms_tiles, ms_far;
+} pars3_profile;
+pars3_status pars3_set_profiling(pars3_matrix *A, int32_t enable);
+pars3_status pars3_get_profile(pars3_matrix *A, pars3_profile *out);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *pars3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARS3_H */

@@ -1,0 +1,269 @@
+"""Skew-symmetric SpMV with reverse Cuthill-McKee reordering on MI355X (gfx950).
+
+Python binding of the C ABI declared in ``include/pars3.h``: the functions
+below carry the same names and only marshal arguments; every step runs in the
+HIP kernels of ``libpars3.so``.  PyTorch provides device memory and streams
+(tensors' ``data_ptr()`` and ``torch.cuda.current_stream().cuda_stream``).
+
+The library is built in-tree by ``python -m paper_2407_17651_amd.build``.  If it
+is missing, importing this package still works but every call raises
+``Pars3Unavailable``: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpars3.so")
+
+# pars3_status
+OK, EINVAL, ENOTLOWER, EUNSORTED, ENOMEM, EHIP, ESTATE, ENOCONV, EBREAKDOWN, ENAN, EIO = range(11)
+STATUS_NAMES = ["OK", "EINVAL", "ENOTLOWER", "EUNSORTED", "ENOMEM", "EHIP", "ESTATE", "ENOCONV", "EBREAKDOWN",
+                "ENAN", "EIO"]
+# pars3_dtype
+F64, F32, BF16 = 0, 1, 2
+ORDER_RCM, ORDER_ORIGINAL = 0, 1
+Y_AUTO, Y_WINDOW, Y_ATOMIC = 0, 1, 2
+
+
+class Pars3Unavailable(RuntimeError):
+    """The HIP library is not built or cannot be loaded."""
+
+
+class Pars3Error(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{where}: {name}: {message}")
+
+
+class SplitParams(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in
+                ("w_in", "t_out", "tile_rows", "window_max", "y_mode", "value_dtype", "keep_fp64", "permute")]
+
+
+class SplitInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("beta", ctypes.c_int32), ("w_in", ctypes.c_int32), ("t_out", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32), ("window_max", ctypes.c_int32), ("y_mode", ctypes.c_int32),
+        ("value_dtype", ctypes.c_int32), ("permute", ctypes.c_int32),
+        ("nnz_inner", ctypes.c_int64), ("nnz_middle", ctypes.c_int64), ("nnz_outer", ctypes.c_int64),
+        ("n_tiles", ctypes.c_int32), ("n_window_tiles", ctypes.c_int32),
+        ("nnz_tiled", ctypes.c_int64), ("nnz_far", ctypes.c_int64),
+        ("n_components", ctypes.c_int32), ("bfs_levels", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64), ("ms_inner", ctypes.c_double), ("ms_tiles", ctypes.c_double),
+                ("ms_far", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_i32, _i64, _d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_st = ctypes.c_int
+
+# name -> (argtypes, restype); the exported C ABI
+SIGNATURES = {
+    "pars3_split_params_default": ([ctypes.POINTER(SplitParams)], None),
+    "pars3_validate": ([_i64, _i64, _vp, _vp], _st),
+    "pars3_create": ([_i64, _i64, _vp, _vp, _vp, ctypes.POINTER(_vp)], _st),
+    "pars3_destroy": ([_vp], None),
+    "pars3_reorder": ([_vp, ctypes.POINTER(SplitParams), _vp], _st),
+    "pars3_spmv": ([_vp, _d, _vp, _vp, _i32, _i32, _i32, _vp], _st),
+    "pars3_get_perm": ([_vp, _vp], _st),
+    "pars3_get_permuted_lower": ([_vp, _vp, _vp, _vp, _vp], _st),
+    "pars3_get_split_info": ([_vp, ctypes.POINTER(SplitInfo)], _st),
+    "pars3_get_values": ([_vp, _i32, _vp], _st),
+    "pars3_set_profiling": ([_vp, _i32], _st),
+    "pars3_get_profile": ([_vp, ctypes.POINTER(Profile)], _st),
+    "pars3_last_error": ([], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libpars3.so`` (raises ``Pars3Unavailable`` if absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise Pars3Unavailable(f"{LIB_PATH} is not built; run python -m paper_2407_17651_amd.build")
+        # PyTorch ships its own HIP runtime.  Loading it first makes the
+        # library bind to that same runtime (it is already loaded under the
+        # soname the library needs), so torch's streams and allocations are
+        # valid in the library's calls and only one runtime owns the device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover - the library also works without torch
+            pass
+        try:
+            L = ctypes.CDLL(LIB_PATH)
+        except OSError as e:  # pragma: no cover - depends on the machine
+            raise Pars3Unavailable(str(e)) from e
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise Pars3Error(status, where, pars3_last_error())
+
+
+def _ptr(a):
+    """Host numpy array or device torch tensor -> address (None for empty)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data if a.size else None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr() if a.numel() else None
+    return int(a)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+# ------------------------------------------------------------------ the C ABI
+def pars3_last_error() -> str:
+    return (lib().pars3_last_error() or b"").decode()
+
+
+def pars3_split_params_default() -> SplitParams:
+    p = SplitParams()
+    lib().pars3_split_params_default(ctypes.byref(p))
+    return p
+
+
+def pars3_validate(n, nnz, rowptr, col) -> int:
+    """Returns the pars3_status of the host-side validation (no device use)."""
+    rp = None if rowptr is None else np.ascontiguousarray(rowptr, np.int32)
+    c = None if col is None else np.ascontiguousarray(col, np.int32)
+    return int(lib().pars3_validate(n, nnz, _ptr(rp), _ptr(c)))
+
+
+def pars3_create(n, nnz, rowptr, col, val):
+    rp = np.ascontiguousarray(rowptr, np.int32)
+    c = np.ascontiguousarray(col, np.int32)
+    v = np.ascontiguousarray(val, np.float64)
+    h = _vp()
+    _check(lib().pars3_create(n, nnz, _ptr(rp), _ptr(c), _ptr(v), ctypes.byref(h)), "pars3_create")
+    return h
+
+
+def pars3_destroy(h):
+    if h:
+        lib().pars3_destroy(h)
+
+
+def pars3_reorder(h, params: SplitParams | None = None, stream=None):
+    _check(lib().pars3_reorder(h, ctypes.byref(params) if params is not None else None, _stream(stream)),
+           "pars3_reorder")
+
+
+def pars3_spmv(h, shift, x, y, k=1, vec_dtype=F64, order=ORDER_RCM, stream=None):
+    _check(lib().pars3_spmv(h, float(shift), _ptr(x), _ptr(y), int(k), int(vec_dtype), int(order), _stream(stream)),
+           "pars3_spmv")
+
+
+def pars3_get_perm(h, n) -> np.ndarray:
+    out = np.zeros(n, np.int32)
+    _check(lib().pars3_get_perm(h, _ptr(out) or _ptr(np.zeros(1, np.int32))), "pars3_get_perm")
+    return out
+
+
+def pars3_get_split_info(h) -> SplitInfo:
+    info = SplitInfo()
+    _check(lib().pars3_get_split_info(h, ctypes.byref(info)), "pars3_get_split_info")
+    return info
+
+
+def pars3_get_permuted_lower(h, n, nnz):
+    rp = np.zeros(n + 1, np.int32)
+    col = np.zeros(nnz, np.int32)
+    val = np.zeros(nnz, np.float64)
+    part = np.zeros(nnz, np.int8)
+    _check(lib().pars3_get_permuted_lower(h, _ptr(rp), _ptr(col), _ptr(val), _ptr(part)), "pars3_get_permuted_lower")
+    return rp, col, val, part
+
+
+def pars3_get_values(h, dtype, nnz) -> np.ndarray:
+    out = np.zeros(nnz, {F64: np.float64, F32: np.float32, BF16: np.uint16}[dtype])
+    if nnz:
+        _check(lib().pars3_get_values(h, int(dtype), _ptr(out)), "pars3_get_values")
+    return out
+
+
+def pars3_set_profiling(h, enable: bool):
+    _check(lib().pars3_set_profiling(h, int(bool(enable))), "pars3_set_profiling")
+
+
+def pars3_get_profile(h) -> dict:
+    p = Profile()
+    _check(lib().pars3_get_profile(h, ctypes.byref(p)), "pars3_get_profile")
+    return {"calls": p.calls, "ms_inner": p.ms_inner, "ms_tiles": p.ms_tiles, "ms_far": p.ms_far}
+
+
+# ------------------------------------------------------------------ convenience wrapper
+class Matrix:
+    """Owning wrapper of a ``pars3_matrix`` handle built from a strictly lower
+    CSR (any object with n, rowptr, col, val)."""
+
+    def __init__(self, L):
+        self.n = int(L.n)
+        self.nnz = int(len(L.col))
+        self.h = pars3_create(self.n, self.nnz, L.rowptr, L.col, L.val)
+
+    def close(self):
+        if self.h:
+            pars3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reorder(self, stream=None, **kw):
+        p = pars3_split_params_default()
+        for k, v in kw.items():
+            setattr(p, k, int(v))
+        pars3_reorder(self.h, p, stream)
+        return self
+
+    def spmv(self, shift, x, y, order=ORDER_RCM, stream=None):
+        import torch
+        k = 1 if x.dim() == 1 else int(x.shape[1])
+        vd = F64 if x.dtype == torch.float64 else F32
+        pars3_spmv(self.h, shift, x, y, k, vd, order, stream)
+        return y
+
+    def perm(self):
+        return pars3_get_perm(self.h, self.n)
+
+    def info(self):
+        return pars3_get_split_info(self.h).as_dict()
+
+    def permuted_lower(self):
+        return pars3_get_permuted_lower(self.h, self.n, self.nnz)
+
+    def values(self, dtype):
+        return pars3_get_values(self.h, dtype, self.nnz)

@@ -1,0 +1,297 @@
+// C ABI entry points: validation, handle life cycle, reorder, product,
+// inspection.  Argument checks run on the host before any device work.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using p3::fail;
+
+extern "C" void pars3_split_params_default(pars3_split_params *p) {
+  if (!p) return;
+  p->w_in = -1;
+  p->t_out = -1;
+  p->tile_rows = 256;
+  p->window_max = 1024;
+  p->y_mode = PARS3_Y_AUTO;
+  p->value_dtype = PARS3_F64;
+  p->keep_fp64 = 0;
+  p->permute = 1;
+}
+
+extern "C" pars3_status pars3_validate(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col) {
+  p3::clear_error();
+  if (n < 0 || nnz < 0 || n > INT32_MAX || nnz > INT32_MAX) return fail(PARS3_EINVAL, "validate: bad n or nnz");
+  if (!rowptr) return fail(PARS3_EINVAL, "validate: rowptr is NULL");
+  if (nnz > 0 && !col) return fail(PARS3_EINVAL, "validate: col is NULL");
+  if (rowptr[0] != 0) return fail(PARS3_EINVAL, "validate: rowptr[0] = %d", rowptr[0]);
+  if ((int64_t)rowptr[n] != nnz) return fail(PARS3_EINVAL, "validate: rowptr[n] = %d, nnz = %lld", rowptr[n], (long long)nnz);
+  for (int64_t i = 0; i < n; i++)
+    if (rowptr[i + 1] < rowptr[i]) return fail(PARS3_EINVAL, "validate: rowptr decreases at row %lld", (long long)i);
+  for (int64_t i = 0; i < n; i++) {
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      if (col[e] < 0 || col[e] >= i)
+        return fail(PARS3_ENOTLOWER, "validate: entry (%lld, %d) is not strictly lower", (long long)i, col[e]);
+      if (e > rowptr[i] && col[e] <= col[e - 1])
+        return fail(PARS3_EUNSORTED, "validate: row %lld has unsorted or duplicate columns", (long long)i);
+    }
+  }
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_create(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                                     const double *val, pars3_matrix **out) {
+  if (!out) return fail(PARS3_EINVAL, "create: out is NULL");
+  *out = nullptr;
+  pars3_status st = pars3_validate(n, nnz, rowptr, col);
+  if (st != PARS3_OK) return st;
+  if (nnz > 0 && !val) return fail(PARS3_EINVAL, "create: val is NULL");
+  pars3_matrix *A = new (std::nothrow) pars3_matrix();
+  if (!A) return fail(PARS3_ENOMEM, "create: host allocation failed");
+  auto bail = [&](pars3_status s) {
+    delete A;
+    return s;
+  };
+  A->n = n;
+  A->nnz = nnz;
+  hipError_t e = hipGetDevice(&A->device);
+  if (e != hipSuccess) return bail(fail(PARS3_EHIP, "create: hipGetDevice: %s", hipGetErrorString(e)));
+  if ((e = A->rowptr.alloc(n + 1)) != hipSuccess || (e = A->col.alloc(nnz)) != hipSuccess ||
+      (e = A->val.alloc(nnz)) != hipSuccess)
+    return bail(fail(PARS3_ENOMEM, "create: device allocation failed: %s", hipGetErrorString(e)));
+  if ((e = hipMemcpy(A->rowptr.p, rowptr, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+      (nnz > 0 && (e = hipMemcpy(A->col.p, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (nnz > 0 && (e = hipMemcpy(A->val.p, val, nnz * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess))
+    return bail(fail(PARS3_EHIP, "create: copy to device failed: %s", hipGetErrorString(e)));
+  *out = A;
+  return PARS3_OK;
+}
+
+pars3_matrix::~pars3_matrix() {
+  for (auto &v : prof.ev)
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
+}
+
+extern "C" void pars3_destroy(pars3_matrix *A) { delete A; }
+
+extern "C" pars3_status pars3_set_profiling(pars3_matrix *A, int32_t enable) {
+  if (!A) return fail(PARS3_EINVAL, "set_profiling: NULL handle");
+  A->prof.on = enable != 0;
+  A->prof.calls = 0;
+  for (int c = 0; c < 3; c++) A->prof.used[c] = 0;
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_get_profile(pars3_matrix *A, pars3_profile *out) {
+  if (!A || !out) return fail(PARS3_EINVAL, "get_profile: NULL argument");
+  auto &P = A->prof;
+  double ms[3] = {0, 0, 0};
+  for (int c = 0; c < 3; c++) {
+    for (int q = 0; q < P.used[c]; q++) {
+      P3_HIP(hipEventSynchronize(P.ev[c][2 * q + 1]));
+      float t = 0.f;
+      P3_HIP(hipEventElapsedTime(&t, P.ev[c][2 * q], P.ev[c][2 * q + 1]));
+      ms[c] += t;
+    }
+    P.used[c] = 0;
+  }
+  out->calls = P.calls;
+  out->ms_inner = ms[0];
+  out->ms_tiles = ms[1];
+  out->ms_far = ms[2];
+  P.calls = 0;
+  return PARS3_OK;
+}
+
+static pars3_status check_params(const pars3_split_params &p) {
+  if (p.w_in < -1 || p.t_out < -1) return fail(PARS3_EINVAL, "reorder: w_in and t_out must be >= -1");
+  if (p.permute != 0 && p.permute != 1) return fail(PARS3_EINVAL, "reorder: permute must be 0 or 1");
+  if (p.keep_fp64 != 0 && p.keep_fp64 != 1) return fail(PARS3_EINVAL, "reorder: keep_fp64 must be 0 or 1");
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *pp, void *stream) {
+  p3::clear_error();
+  if (!A) return fail(PARS3_EINVAL, "reorder: NULL handle");
+  pars3_split_params p;
+  if (pp) p = *pp;
+  else pars3_split_params_default(&p);
+  P3_TRY(check_params(p));
+  hipStream_t s = (hipStream_t)stream;
+  P3_HIP(hipSetDevice(A->device));
+  if (!A->perm_done || A->perm_kind != p.permute) {
+    A->perm_done = false;
+    A->split_done = false;
+    if (p.permute) P3_TRY(p3::rcm_gpu(A, s));
+    else P3_TRY(p3::identity_perm_gpu(A, s));
+    P3_TRY(p3::permute_gpu(A, s));
+    A->perm_done = true;
+    A->perm_kind = p.permute;
+  }
+  A->split_done = false;
+  P3_TRY(p3::split_and_layout(A, p, s));
+  P3_HIP(hipStreamSynchronize(s));
+  A->split_done = true;
+  return PARS3_OK;
+}
+
+static bool overlap(const void *a, const void *b, size_t bytes) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+extern "C" pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x, void *y, int32_t k, int32_t vec_dtype,
+                                   int32_t order, void *stream) {
+  if (!A) return fail(PARS3_EINVAL, "spmv: NULL handle");
+  if (!A->split_done) return fail(PARS3_ESTATE, "spmv: call pars3_reorder first");
+  if (k != 1 && k != 2 && k != 4 && k != 8) return fail(PARS3_EINVAL, "spmv: k must be 1, 2, 4 or 8");
+  if (vec_dtype != PARS3_F64 && vec_dtype != PARS3_F32) return fail(PARS3_EINVAL, "spmv: bad vec_dtype");
+  if (order != PARS3_ORDER_RCM && order != PARS3_ORDER_ORIGINAL) return fail(PARS3_EINVAL, "spmv: bad order");
+  if (A->n == 0) return PARS3_OK;
+  if (!x || !y) return fail(PARS3_EINVAL, "spmv: NULL vector");
+  const size_t elem = vec_dtype == PARS3_F64 ? 8 : 4;
+  const size_t bytes = (size_t)A->n * k * elem;
+  if (overlap(x, y, bytes)) return fail(PARS3_EINVAL, "spmv: x and y overlap");
+  hipStream_t s = (hipStream_t)stream;
+  if (order == PARS3_ORDER_RCM) return p3::spmv_rcm(A, shift, x, y, k, vec_dtype, s);
+  if (A->xr.n < bytes) {
+    P3_HIP(hipStreamSynchronize(s));
+    P3_HIP(A->xr.alloc(bytes));
+    P3_HIP(A->yr.alloc(bytes));
+  }
+  P3_TRY(p3::gather_rows(x, A->xr.p, A->perm.p, A->n, k, elem, s));
+  P3_TRY(p3::spmv_rcm(A, shift, A->xr.p, A->yr.p, k, vec_dtype, s));
+  P3_TRY(p3::scatter_rows(A->yr.p, y, A->perm.p, A->n, k, elem, s));
+  return PARS3_OK;
+}
+
+// ------------------------------------------------------------ inspection
+extern "C" pars3_status pars3_get_perm(const pars3_matrix *A, int32_t *perm) {
+  if (!A || !perm) return fail(PARS3_EINVAL, "get_perm: NULL argument");
+  if (!A->perm_done) return fail(PARS3_ESTATE, "get_perm: call pars3_reorder first");
+  if (A->n) P3_HIP(hipMemcpy(perm, A->perm.p, A->n * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_get_permuted_lower(const pars3_matrix *A, int32_t *rowptr, int32_t *col, double *val,
+                                                 int8_t *part) {
+  if (!A) return fail(PARS3_EINVAL, "get_permuted_lower: NULL handle");
+  if (!A->split_done) return fail(PARS3_ESTATE, "get_permuted_lower: call pars3_reorder first");
+  if (rowptr) P3_HIP(hipMemcpy(rowptr, A->prow.p, (A->n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (A->nnz) {
+    if (col) P3_HIP(hipMemcpy(col, A->pcol.p, A->nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (val) P3_HIP(hipMemcpy(val, A->pval.p, A->nnz * sizeof(double), hipMemcpyDeviceToHost));
+    if (part) P3_HIP(hipMemcpy(part, A->part.p, A->nnz * sizeof(int8_t), hipMemcpyDeviceToHost));
+  }
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_get_split_info(const pars3_matrix *A, pars3_split_info *info) {
+  if (!A || !info) return fail(PARS3_EINVAL, "get_split_info: NULL argument");
+  if (!A->split_done) return fail(PARS3_ESTATE, "get_split_info: call pars3_reorder first");
+  const p3::layout &L = A->lay;
+  std::memset(info, 0, sizeof(*info));
+  info->n = A->n;
+  info->nnz = A->nnz;
+  info->beta = A->beta;
+  info->w_in = L.w_in;
+  info->t_out = L.t_out;
+  info->tile_rows = L.T;
+  info->window_max = L.wmax;
+  info->y_mode = L.y_mode;
+  info->value_dtype = L.vdtype;
+  info->permute = A->perm_kind;
+  info->nnz_inner = A->cnt[0];
+  info->nnz_middle = A->cnt[1];
+  info->nnz_outer = A->cnt[2];
+  info->n_tiles = L.ntiles;
+  info->n_window_tiles = L.n_window_tiles;
+  info->nnz_tiled = L.nnz_tiled;
+  info->nnz_far = L.nnz_far;
+  info->n_components = A->ncomp;
+  info->bfs_levels = A->nlevels;
+  return PARS3_OK;
+}
+
+// The stored values of one precision, gathered back into canonical CSR order.
+namespace p3 {
+template <class V>
+__global__ void k_collect(const int32_t *__restrict__ prow, const int32_t *__restrict__ pcol,
+                          const int8_t *__restrict__ part, int32_t n, int32_t T, const int32_t *__restrict__ tile_ptr,
+                          const int32_t *__restrict__ tile_alo, const int32_t *__restrict__ tile_la,
+                          const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
+                          const int32_t *__restrict__ far_row, const int32_t *__restrict__ far_col,
+                          const V *__restrict__ far_v, int64_t nfar, const V *__restrict__ in_v, V *__restrict__ out) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t t = i / T, r0 = t * T;
+  for (int32_t e = prow[i]; e < prow[i + 1]; e++) {
+    const int32_t j = pcol[e];
+    V v = (V)0;
+    bool found = false;
+    if (part[e] == 0) {
+      v = in_v[(int64_t)(i - j - 1) * n + i];
+      found = true;
+    }
+    if (!found) {
+      const int32_t la = tile_la[t], alo = tile_alo[t];
+      const uint32_t want_slot = j >= r0 ? (uint32_t)(la + (j - r0)) : (uint32_t)(j - alo);
+      const uint32_t key = ((uint32_t)(i - r0) << 16) | want_slot;
+      const bool in_window = j >= r0 || (la > 0 && j >= alo && j < alo + la);
+      if (part[e] == 1 && in_window) {
+        for (int32_t q = tile_ptr[t]; q < tile_ptr[t + 1]; q++)
+          if (ent_rc[q] == key) {
+            v = ent_v[q];
+            found = true;
+            break;
+          }
+      }
+    }
+    if (!found) {
+      // coordinate list is sorted by row: binary search for the row, then scan
+      int64_t lo = 0, hi = nfar;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (far_row[mid] < i) lo = mid + 1;
+        else hi = mid;
+      }
+      for (int64_t q = lo; q < nfar && far_row[q] == i; q++)
+        if (far_col[q] == j) {
+          v = far_v[q];
+          break;
+        }
+    }
+    out[e] = v;
+  }
+}
+}  // namespace p3
+
+extern "C" pars3_status pars3_get_values(const pars3_matrix *A, int32_t dtype, void *host) {
+  if (!A || !host) return fail(PARS3_EINVAL, "get_values: NULL argument");
+  if (!A->split_done) return fail(PARS3_ESTATE, "get_values: call pars3_reorder first");
+  const p3::layout &L = A->lay;
+  const int32_t n = (int32_t)A->n;
+  if (A->nnz == 0) return PARS3_OK;
+  size_t elem = dtype == PARS3_F64 ? 8 : dtype == PARS3_F32 ? 4 : 2;
+  p3::dbuf<char> out;
+  P3_HIP(out.alloc(A->nnz * elem));
+  unsigned g = (unsigned)p3::cdiv(n, 256);
+  if (dtype == PARS3_F64 && A->has_f64)
+    p3::k_collect<double><<<g, 256>>>(A->prow.p, A->pcol.p, A->part.p, n, L.T, L.tile_ptr.p, L.tile_alo.p,
+                                      L.tile_la.p, L.ent_rc.p, L.ent_f64.p, L.far_row.p, L.far_col.p, L.far_f64.p,
+                                      L.nnz_far, L.in_f64.p, (double *)out.p);
+  else if (dtype == PARS3_F32 && A->has_f32)
+    p3::k_collect<float><<<g, 256>>>(A->prow.p, A->pcol.p, A->part.p, n, L.T, L.tile_ptr.p, L.tile_alo.p, L.tile_la.p,
+                                     L.ent_rc.p, L.ent_f32.p, L.far_row.p, L.far_col.p, L.far_f32.p, L.nnz_far,
+                                     L.in_f32.p, (float *)out.p);
+  else if (dtype == PARS3_BF16 && A->has_bf16)
+    p3::k_collect<uint16_t><<<g, 256>>>(A->prow.p, A->pcol.p, A->part.p, n, L.T, L.tile_ptr.p, L.tile_alo.p,
+                                        L.tile_la.p, L.ent_rc.p, L.ent_bf16.p, L.far_row.p, L.far_col.p, L.far_bf16.p,
+                                        L.nnz_far, L.in_bf16.p, (uint16_t *)out.p);
+  else
+    return fail(PARS3_ESTATE, "get_values: precision %d is not stored", dtype);
+  P3_LAUNCHED();
+  P3_HIP(hipMemcpy(host, out.p, A->nnz * elem, hipMemcpyDeviceToHost));
+  return PARS3_OK;
+}

@@ -1,0 +1,218 @@
+// Internal declarations of the pars3 library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <vector>
+
+#include "pars3.h"
+
+namespace p3 {
+
+// ---------------------------------------------------------------- errors
+pars3_status fail(pars3_status st, const char *fmt, ...);
+void clear_error();
+
+#define P3_HIP(call)                                                                                    \
+  do {                                                                                                  \
+    hipError_t e_ = (call);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      return ::p3::fail(e_ == hipErrorOutOfMemory ? PARS3_ENOMEM : PARS3_EHIP, "%s: %s (%s:%d)", #call, \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                                     \
+  } while (0)
+
+#define P3_TRY(expr)                     \
+  do {                                   \
+    pars3_status s_ = (expr);            \
+    if (s_ != PARS3_OK) return s_;       \
+  } while (0)
+
+// Launch check: reports launch-configuration errors immediately.
+#define P3_LAUNCHED() P3_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- device buffers
+template <class T>
+struct dbuf {
+  T *p = nullptr;
+  size_t n = 0;
+  dbuf() = default;
+  dbuf(const dbuf &) = delete;
+  dbuf &operator=(const dbuf &) = delete;
+  ~dbuf() { release(); }
+  hipError_t alloc(size_t m) {
+    release();
+    n = m;
+    return hipMalloc((void **)&p, (m ? m : 1) * sizeof(T));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int bits_for(uint64_t v) {  // bits needed to hold values 0..v
+  int b = 0;
+  while (v) {
+    b++;
+    v >>= 1;
+  }
+  return b;
+}
+
+// ---------------------------------------------------------------- wave-aggregated atomics
+// When every valid lane of the wavefront targets the same address, the lanes
+// combine their values with shuffles and one lane issues the atomic;
+// otherwise each valid lane issues its own.  All 64 lanes must call these
+// (lanes without work pass valid = false), so callers must not return early.
+__device__ __forceinline__ int wave_uniform_leader(int64_t idx, bool valid, int64_t *i0) {
+  const unsigned long long m = __ballot(valid);
+  if (m == 0ull) return -1;
+  const int l = __ffsll((long long)m) - 1;
+  *i0 = __shfl(idx, l, 64);
+  return __all(!valid || idx == *i0) ? l : -2;
+}
+template <class T>
+__device__ __forceinline__ void agg_atomic_add(T *base, int64_t idx, T v, bool valid) {
+  int64_t i0 = 0;
+  const int l = wave_uniform_leader(idx, valid, &i0);
+  if (l == -1) return;
+  if (l >= 0) {
+    T s = valid ? v : (T)0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((int)(threadIdx.x & 63) == l) atomicAdd(&base[i0], s);
+  } else if (valid) {
+    atomicAdd(&base[idx], v);
+  }
+}
+template <class T>
+__device__ __forceinline__ void agg_atomic_min(T *base, int64_t idx, T v, bool valid, T ident) {
+  int64_t i0 = 0;
+  const int l = wave_uniform_leader(idx, valid, &i0);
+  if (l == -1) return;
+  if (l >= 0) {
+    T s = valid ? v : ident;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      T o = __shfl_xor(s, off, 64);
+      s = o < s ? o : s;
+    }
+    if ((int)(threadIdx.x & 63) == l) atomicMin(&base[i0], s);
+  } else if (valid) {
+    atomicMin(&base[idx], v);
+  }
+}
+template <class T>
+__device__ __forceinline__ void agg_atomic_max(T *base, int64_t idx, T v, bool valid, T ident) {
+  int64_t i0 = 0;
+  const int l = wave_uniform_leader(idx, valid, &i0);
+  if (l == -1) return;
+  if (l >= 0) {
+    T s = valid ? v : ident;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      T o = __shfl_xor(s, off, 64);
+      s = o > s ? o : s;
+    }
+    if ((int)(threadIdx.x & 63) == l) atomicMax(&base[i0], s);
+  } else if (valid) {
+    atomicMax(&base[idx], v);
+  }
+}
+
+// ---------------------------------------------------------------- primitives (util.hip)
+// Exclusive prefix sum of in[0..m) into out[0..m]; out[m] = total.  in and
+// out must not overlap.  Asynchronous on `s`.
+pars3_status scan_i32(const int32_t *in, int32_t *out, int64_t m, hipStream_t s);
+pars3_status scan_i64(const int64_t *in, int64_t *out, int64_t m, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on the low `key_bits` bits of
+// the keys.  Sorted pairs end in (k0, v0); k1/v1 are scratch of the same size.
+pars3_status radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t m, int key_bits,
+                              hipStream_t s);
+// Integer fill helpers.
+pars3_status fill_i32(int32_t *p, int32_t v, int64_t m, hipStream_t s);
+pars3_status fill_u64(uint64_t *p, uint64_t v, int64_t m, hipStream_t s);
+pars3_status iota_i32(int32_t *p, int64_t m, hipStream_t s);
+
+// ---------------------------------------------------------------- stored layouts
+// One SpMV layout: the three parts of the split arranged for the kernels.
+struct layout {
+  int32_t T = 256, wmax = 1024, y_mode = 0, w_in = 0, t_out = 0;
+  int32_t ntiles = 0, n_window_tiles = 0;
+  int32_t max_slots = 0;  // max over tiles of (back window + tile rows)
+  int64_t nnz_tiled = 0, nnz_far = 0;
+  int32_t vdtype = PARS3_F64;
+  // inner band, diagonal-major: value of (i, i-k) at [(k-1)*n + i]
+  dbuf<double> in_f64;
+  dbuf<float> in_f32;
+  dbuf<uint16_t> in_bf16;
+  // tiles of T rows: entries [tile_ptr[t], tile_ptr[t+1]); back window
+  // columns [tile_alo[t], tile_alo[t] + tile_la[t])
+  dbuf<int32_t> tile_ptr, tile_alo, tile_la;
+  dbuf<uint32_t> ent_rc;  // (row - r0) << 16 | slot
+  dbuf<double> ent_f64;
+  dbuf<float> ent_f32;
+  dbuf<uint16_t> ent_bf16;
+  // coordinate list (outer part plus middle entries outside tile windows)
+  dbuf<int32_t> far_row, far_col;
+  dbuf<double> far_f64;
+  dbuf<float> far_f32;
+  dbuf<uint16_t> far_bf16;
+};
+
+}  // namespace p3
+
+struct pars3_matrix {
+  int64_t n = 0, nnz = 0;
+  int device = 0;
+  // input, original numbering
+  p3::dbuf<int32_t> rowptr, col;
+  p3::dbuf<double> val;
+  // reordering
+  bool perm_done = false;
+  int32_t perm_kind = -1;  // 1 RCM, 0 identity
+  int32_t ncomp = 0, nlevels = 0;
+  p3::dbuf<int32_t> perm, iperm;
+  // permuted strictly lower CSR, FP64, canonical order
+  p3::dbuf<int32_t> prow, pcol;
+  p3::dbuf<double> pval;
+  p3::dbuf<int8_t> part;
+  int32_t beta = 0;
+  int64_t cnt[3] = {0, 0, 0};
+  bool split_done = false;
+  pars3_split_params params{};
+  p3::layout lay;
+  bool has_f64 = false, has_f32 = false, has_bf16 = false;
+  // scratch for products in the caller's numbering
+  p3::dbuf<char> xr, yr;
+  // per-kernel event timing (pars3_set_profiling)
+  struct {
+    bool on = false;
+    int64_t calls = 0;
+    int used[3] = {0, 0, 0};
+    std::vector<hipEvent_t> ev[3];  // pairs: [2q] start, [2q+1] stop
+  } prof;
+  ~pars3_matrix();
+};
+
+namespace p3 {
+// reorder.hip
+pars3_status rcm_gpu(pars3_matrix *A, hipStream_t s);
+pars3_status identity_perm_gpu(pars3_matrix *A, hipStream_t s);
+pars3_status permute_gpu(pars3_matrix *A, hipStream_t s);
+// layout.hip
+pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipStream_t s);
+// spmv.hip
+enum { PROF_INNER = 0, PROF_TILES = 1, PROF_FAR = 2 };
+pars3_status prof_mark(pars3_matrix *A, int cls, int stop, hipStream_t s);
+pars3_status spmv_rcm(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, hipStream_t s);
+pars3_status gather_rows(const void *src, void *dst, const int32_t *idx, int64_t n, int k, size_t elem,
+                         hipStream_t s);
+pars3_status scatter_rows(const void *src, void *dst, const int32_t *idx, int64_t n, int k, size_t elem,
+                          hipStream_t s);
+}  // namespace p3

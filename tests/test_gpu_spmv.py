@@ -1,0 +1,144 @@
+"""GPU skew-symmetric product against the oracle's full-CSR FP64 product.
+
+Bars: FP64 <= 1e-12, FP32 <= 1e-5 and BF16 <= 1e-5 relative infinity-norm error
+against the oracle run on the same rounded values and vectors; integer-valued
+inputs bit-exact in every precision (every partial sum is an exact integer)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2407_17651_amd as p3
+import synth
+from gpu_util import gpu_spmv, oracle_reordered, rel_inf, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {p3.F64: 1e-12, p3.F32: 1e-5, p3.BF16: 1e-5}
+
+
+def check_product(L, shift=0.5, k=1, value_dtype=p3.F64, seed=11, **params):
+    perm, B = oracle_reordered(L) if params.get("permute", 1) else (None, L)
+    M = p3.Matrix(L).reorder(value_dtype=value_dtype, **params)
+    x = synth.vector(L.n, seed, k)
+    vec = p3.F64 if value_dtype == p3.F64 else p3.F32
+    xr = x if vec == p3.F64 else x.astype(np.float32).astype(np.float64)
+    Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, {0: "f64", 1: "f32", 2: "bf16"}[value_dtype])})
+    want = oracle.spmv(Bv, shift, xr)
+    got = gpu_spmv(M, shift, x, vec)
+    err = rel_inf(got, want)
+    assert err <= TOL[value_dtype], err
+    return M, err
+
+
+@pytest.mark.parametrize("name,maker", [
+    ("workload0", lambda: synth.workload(0)),
+    ("grid3d_20", lambda: synth.grid3d(20, 3, "normal")),
+    ("rgg_30000", lambda: synth.rgg2d(30000, 16.0, 4)),
+    ("chung_lu_20000", lambda: synth.chung_lu(20000, 16.0, 2.5, 5)),
+    ("pieces", lambda: synth.from_edges(40, [(i, i + 1) for i in range(0, 38, 3)], relabel=True, seed=3)),
+])
+@pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32, p3.BF16])
+def test_product_parity(name, maker, value_dtype):
+    print(f"[gpu] spmv {name} dtype={value_dtype}", flush=True)
+    check_product(maker(), value_dtype=value_dtype)
+
+
+@pytest.mark.parametrize("params", [
+    dict(tile_rows=64), dict(tile_rows=1024), dict(window_max=64), dict(y_mode=p3.Y_ATOMIC),
+    dict(w_in=4), dict(w_in=16, t_out=40), dict(t_out=5), dict(w_in=0, t_out=0), dict(permute=0),
+])
+def test_layout_variants(params):
+    print(f"[gpu] spmv layout {params}", flush=True)
+    check_product(synth.rgg2d(20000, 12.0, 8), shift=-0.25, **params)
+
+
+@pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32, p3.BF16])
+@pytest.mark.parametrize("params", [dict(), dict(w_in=3), dict(y_mode=p3.Y_ATOMIC), dict(tile_rows=64, window_max=32)])
+def test_integer_inputs_bit_exact(value_dtype, params):
+    """Values and x in {-4..4}: exact in every precision and summation order."""
+    L = synth.rgg2d(8000, 10.0, 12, "int4")
+    print(f"[gpu] spmv integer dtype={value_dtype} {params}", flush=True)
+    perm, B = oracle_reordered(L)
+    M = p3.Matrix(L).reorder(value_dtype=value_dtype, **params)
+    x = np.floor(synth.vector(L.n, 3) * 4.999)
+    want = oracle.spmv(B, 2.0, x)
+    vec = p3.F64 if value_dtype == p3.F64 else p3.F32
+    got = gpu_spmv(M, 2.0, x, vec)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("k", [2, 4, 8])
+@pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32])
+def test_block_right_hand_sides(k, value_dtype):
+    L = synth.grid3d(16, 21, "normal")
+    print(f"[gpu] spmv k={k} dtype={value_dtype}", flush=True)
+    perm, B = oracle_reordered(L)
+    M = p3.Matrix(L).reorder(value_dtype=value_dtype)
+    X = synth.vector(L.n, 5, k)
+    vec = p3.F64 if value_dtype == p3.F64 else p3.F32
+    Xr = X if vec == p3.F64 else X.astype(np.float32).astype(np.float64)
+    Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, "f64" if vec == p3.F64 else "f32")})
+    want = oracle.spmv(Bv, 0.75, Xr)
+    got = gpu_spmv(M, 0.75, X, vec)
+    assert rel_inf(got, want) <= TOL[value_dtype]
+    # each column equals the single right-hand-side product
+    for c in range(k):
+        one = gpu_spmv(M, 0.75, np.ascontiguousarray(X[:, c]), vec)
+        assert rel_inf(got[:, c], one) <= TOL[value_dtype]
+
+
+def test_original_order():
+    L = synth.rgg2d(10000, 10.0, 14)
+    M = p3.Matrix(L).reorder()
+    x = synth.vector(L.n, 8)
+    got = gpu_spmv(M, 1.5, x, p3.F64, p3.ORDER_ORIGINAL)
+    assert rel_inf(got, oracle.spmv(L, 1.5, x)) <= 1e-12
+
+
+def test_worked_example():
+    """Section 3.1.2, eqs. (2)-(6): only A30 stored."""
+    L = synth.Lower(4, np.array([0, 0, 0, 0, 1], np.int32), np.array([0], np.int32), np.array([2.5]))
+    M = p3.Matrix(L).reorder(permute=0)
+    got = gpu_spmv(M, 0.0, np.array([3.0, -1.0, 7.0, -2.0]))
+    assert got.tolist() == [5.0, 0.0, 0.0, 7.5]
+
+
+def test_degenerate_sizes():
+    for L in (synth.from_edges(1, []), synth.from_edges(6, []), synth.Lower(0, np.zeros(1, np.int32),
+                                                                              np.zeros(0, np.int32), np.zeros(0))):
+        M = p3.Matrix(L).reorder()
+        if L.n:
+            x = synth.vector(L.n, 1)
+            assert np.array_equal(gpu_spmv(M, 0.5, x), 0.5 * x)
+
+
+def test_errors():
+    L = synth.grid2d(8, 1)
+    M = p3.Matrix(L)
+    x = to_dev(np.ones(L.n))
+    with pytest.raises(p3.Pars3Error) as e:
+        p3.pars3_spmv(M.h, 0.0, x, x.clone(), 1, p3.F64, p3.ORDER_RCM)
+    assert e.value.status == p3.ESTATE
+    M.reorder()
+    with pytest.raises(p3.Pars3Error) as e:
+        p3.pars3_spmv(M.h, 0.0, x, x, 1, p3.F64, p3.ORDER_RCM)
+    assert e.value.status == p3.EINVAL
+    with pytest.raises(p3.Pars3Error) as e:
+        p3.pars3_spmv(M.h, 0.0, x, x.clone(), 3, p3.F64, p3.ORDER_RCM)
+    assert e.value.status == p3.EINVAL
+    with pytest.raises(p3.Pars3Error) as e:
+        p3.pars3_spmv(M.h, 0.0, x.float(), x.float().clone(), 1, p3.F32, p3.ORDER_RCM)
+    assert e.value.status == p3.ESTATE
+    with pytest.raises(p3.Pars3Error) as e:
+        p3.pars3_create(3, 1, np.array([0, 0, 0, 1], np.int32), np.array([2], np.int32), np.ones(1))
+    assert e.value.status == p3.ENOTLOWER
+
+
+def test_workload1_full_size_fp64():
+    """The benchmark workload (3D 128^3, N(0,1) values) in the benchmark's
+    launch configuration, every output compared with the oracle."""
+    L = synth.workload(1)
+    print("[gpu] spmv workload1 fp64", flush=True)
+    M, err = check_product(L, shift=0.5, value_dtype=p3.F64, seed=1101)
+    print(f"[gpu] workload1 fp64 rel err {err:.3e}", flush=True)
