@@ -51,8 +51,6 @@ typedef enum { PARS3_F64 = 0, PARS3_F32 = 1, PARS3_BF16 = 2 } pars3_dtype;
 
 enum { PARS3_ORDER_RCM = 0, PARS3_ORDER_ORIGINAL = 1 };
 
-enum { PARS3_Y_AUTO = 0, PARS3_Y_WINDOW = 1, PARS3_Y_ATOMIC = 2 };
-
 typedef struct pars3_matrix pars3_matrix;
 
 /* Split and layout parameters of pars3_reorder (Sections 1 and 3.1.2: the
@@ -62,13 +60,14 @@ typedef struct pars3_matrix pars3_matrix;
  *   inner  : d <= w_in            (w_in = 0: only the diagonal, i.e. the shift)
  *   middle : w_in < d <= t_out
  *   outer  : d > t_out
- * Fields set to -1 (or 0 where noted) take the defaults. */
+ * The inner part is stored diagonal-major without indices; the middle and
+ * outer parts are stored in tile-pair blocks of tile_rows x tile_rows (the
+ * outer part in blocks of its own).  Fields set to -1 (or 0 where noted) take
+ * the defaults. */
 typedef struct {
-  int32_t w_in;        /* inner half-width >= 0; -1 = 0 (the paper's diagonal split) */
+  int32_t w_in;        /* inner half-width, 0..64; -1 = 0 (the paper's diagonal split) */
   int32_t t_out;       /* middle/outer boundary; -1 = max(beta - 3, 0) ("outer bandwidth 3") */
   int32_t tile_rows;   /* rows per tile: 64, 128, 256, 512 or 1024; 0 = 256 */
-  int32_t window_max;  /* max length of a tile's back window of columns; 0 = 1024 */
-  int32_t y_mode;      /* PARS3_Y_AUTO/WINDOW: LDS windows where they fit; PARS3_Y_ATOMIC: none */
   int32_t value_dtype; /* pars3_dtype of the stored values used by pars3_spmv */
   int32_t keep_fp64;   /* also keep FP64 values (needed by the mixed-precision solver) */
   int32_t permute;     /* 1 = reverse Cuthill-McKee (default); 0 = keep the given order */
@@ -82,14 +81,13 @@ typedef struct {
   int64_t n, nnz;
   int32_t beta;        /* max d after reordering (the RCM bandwidth) */
   int32_t w_in, t_out; /* resolved split parameters */
-  int32_t tile_rows, window_max, y_mode, value_dtype, permute;
+  int32_t tile_rows, value_dtype, permute;
   int64_t nnz_inner, nnz_middle, nnz_outer; /* the three parts, by definition */
   int32_t n_tiles;
-  int32_t n_window_tiles;   /* tiles whose back window is held in LDS */
-  int64_t nnz_tiled;        /* entries processed by the tile kernel */
-  int64_t nnz_far;          /* entries processed by the coordinate kernel */
-  int32_t n_components;     /* connected components of the graph of S */
-  int32_t bfs_levels;       /* levels of the Cuthill-McKee search (max over components) */
+  int32_t n_blocks;          /* non-empty tile-pair blocks (middle and outer) */
+  int32_t max_blocks;        /* max over tiles of blocks read on one side */
+  int32_t n_components;      /* connected components of the graph of S */
+  int32_t bfs_levels;        /* levels of the Cuthill-McKee search (max over components) */
 } pars3_split_info;
 
 /* Host-only validation of a strictly lower CSR (no device use).  Checks, rows
@@ -148,15 +146,32 @@ pars3_status pars3_get_values(const pars3_matrix *A, int32_t dtype, void *host);
  * kernel that pars3_spmv launches is bracketed by two hipEvents recorded on the
  * launch stream (at most 4096 products between reads; later ones are not
  * timed).  pars3_get_profile waits for the recorded events, returns the summed
- * durations in milliseconds per kernel class (inner-band/initialisation, tile,
- * coordinate-list) and the number of timed products, then resets the
- * counters. */
+ * durations in milliseconds per kernel class (ms_band: the product kernel;
+ * ms_fixup: work in the caller's numbering, gather and scatter; ms_other:
+ * reserved) and the number of timed products, then resets the counters. */
 typedef struct {
   int64_t calls;
-  double ms_inner, ms_tiles, ms_far;
+  double ms_band, ms_fixup, ms_other;
 } pars3_profile;
 pars3_status pars3_set_profiling(pars3_matrix *A, int32_t enable);
 pars3_status pars3_get_profile(pars3_matrix *A, pars3_profile *out);
+
+/* Full-CSR comparison path (the storage that keeps every nonzero, Section 1).
+ * pars3_csr_create builds, on the GPU, the full CSR of S (both triangles,
+ * 2*nnz entries, columns ascending in every row) in the reordered numbering
+ * (order = PARS3_ORDER_RCM, after pars3_reorder) or in the caller's numbering
+ * (PARS3_ORDER_ORIGINAL), with FP64 or FP32 values (value_dtype).  Synchronous.
+ * pars3_csr_spmv computes y = shift*x + S*x (device vectors of n values of the
+ * value precision, x != y) with engine 0 = this library's CSR-vector kernel
+ * (a power-of-two group of lanes per row) or engine 1 = rocSPARSE's CSR
+ * product (default algorithm; shift must be 0 there).  Asynchronous.
+ * pars3_csr_get copies the CSR (FP64 values) to caller-allocated host arrays
+ * rowptr[n+1], col[2*nnz], val[2*nnz]; NULL outputs are skipped. */
+typedef struct pars3_csr pars3_csr;
+pars3_status pars3_csr_create(const pars3_matrix *A, int32_t order, int32_t value_dtype, pars3_csr **out);
+pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x, void *y, int32_t engine, void *stream);
+pars3_status pars3_csr_get(const pars3_csr *C, int32_t *rowptr, int32_t *col, double *val);
+void pars3_csr_destroy(pars3_csr *C);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *pars3_last_error(void);

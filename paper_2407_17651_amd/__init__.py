@@ -26,7 +26,6 @@ STATUS_NAMES = ["OK", "EINVAL", "ENOTLOWER", "EUNSORTED", "ENOMEM", "EHIP", "EST
 # pars3_dtype
 F64, F32, BF16 = 0, 1, 2
 ORDER_RCM, ORDER_ORIGINAL = 0, 1
-Y_AUTO, Y_WINDOW, Y_ATOMIC = 0, 1, 2
 
 
 class Pars3Unavailable(RuntimeError):
@@ -41,19 +40,16 @@ class Pars3Error(RuntimeError):
 
 
 class SplitParams(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int32) for f in
-                ("w_in", "t_out", "tile_rows", "window_max", "y_mode", "value_dtype", "keep_fp64", "permute")]
+    _fields_ = [(f, ctypes.c_int32) for f in ("w_in", "t_out", "tile_rows", "value_dtype", "keep_fp64", "permute")]
 
 
 class SplitInfo(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
         ("beta", ctypes.c_int32), ("w_in", ctypes.c_int32), ("t_out", ctypes.c_int32),
-        ("tile_rows", ctypes.c_int32), ("window_max", ctypes.c_int32), ("y_mode", ctypes.c_int32),
-        ("value_dtype", ctypes.c_int32), ("permute", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32), ("value_dtype", ctypes.c_int32), ("permute", ctypes.c_int32),
         ("nnz_inner", ctypes.c_int64), ("nnz_middle", ctypes.c_int64), ("nnz_outer", ctypes.c_int64),
-        ("n_tiles", ctypes.c_int32), ("n_window_tiles", ctypes.c_int32),
-        ("nnz_tiled", ctypes.c_int64), ("nnz_far", ctypes.c_int64),
+        ("n_tiles", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
         ("n_components", ctypes.c_int32), ("bfs_levels", ctypes.c_int32),
     ]
 
@@ -62,8 +58,8 @@ class SplitInfo(ctypes.Structure):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("calls", ctypes.c_int64), ("ms_inner", ctypes.c_double), ("ms_tiles", ctypes.c_double),
-                ("ms_far", ctypes.c_double)]
+    _fields_ = [("calls", ctypes.c_int64), ("ms_band", ctypes.c_double), ("ms_fixup", ctypes.c_double),
+                ("ms_other", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -84,6 +80,10 @@ SIGNATURES = {
     "pars3_get_values": ([_vp, _i32, _vp], _st),
     "pars3_set_profiling": ([_vp, _i32], _st),
     "pars3_get_profile": ([_vp, ctypes.POINTER(Profile)], _st),
+    "pars3_csr_create": ([_vp, _i32, _i32, ctypes.POINTER(_vp)], _st),
+    "pars3_csr_spmv": ([_vp, _d, _vp, _vp, _i32, _vp], _st),
+    "pars3_csr_get": ([_vp, _vp, _vp, _vp], _st),
+    "pars3_csr_destroy": ([_vp], None),
     "pars3_last_error": ([], ctypes.c_char_p),
 }
 
@@ -218,7 +218,30 @@ def pars3_set_profiling(h, enable: bool):
 def pars3_get_profile(h) -> dict:
     p = Profile()
     _check(lib().pars3_get_profile(h, ctypes.byref(p)), "pars3_get_profile")
-    return {"calls": p.calls, "ms_inner": p.ms_inner, "ms_tiles": p.ms_tiles, "ms_far": p.ms_far}
+    return {"calls": p.calls, "ms_band": p.ms_band, "ms_fixup": p.ms_fixup, "ms_other": p.ms_other}
+
+
+def pars3_csr_create(h, order=ORDER_RCM, value_dtype=F64):
+    c = _vp()
+    _check(lib().pars3_csr_create(h, int(order), int(value_dtype), ctypes.byref(c)), "pars3_csr_create")
+    return c
+
+
+def pars3_csr_spmv(c, shift, x, y, engine=0, stream=None):
+    _check(lib().pars3_csr_spmv(c, float(shift), _ptr(x), _ptr(y), int(engine), _stream(stream)), "pars3_csr_spmv")
+
+
+def pars3_csr_get(c, n, nnz_full):
+    rp = np.zeros(n + 1, np.int32)
+    col = np.zeros(nnz_full, np.int32)
+    val = np.zeros(nnz_full, np.float64)
+    _check(lib().pars3_csr_get(c, _ptr(rp), _ptr(col), _ptr(val)), "pars3_csr_get")
+    return rp, col, val
+
+
+def pars3_csr_destroy(c):
+    if c:
+        lib().pars3_csr_destroy(c)
 
 
 # ------------------------------------------------------------------ convenience wrapper

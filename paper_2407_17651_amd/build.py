@@ -23,7 +23,7 @@ FLAGS = [
     "-munsafe-fp-atomics",
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument",
+    "-Wno-unused-command-line-argument", "-Wno-deprecated-declarations",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 LIBS = ["-L/opt/rocm/lib", "-lrocsparse", "-Wl,-rpath,/opt/rocm/lib"]

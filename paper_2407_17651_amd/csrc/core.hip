@@ -13,8 +13,6 @@ extern "C" void pars3_split_params_default(pars3_split_params *p) {
   p->w_in = -1;
   p->t_out = -1;
   p->tile_rows = 256;
-  p->window_max = 1024;
-  p->y_mode = PARS3_Y_AUTO;
   p->value_dtype = PARS3_F64;
   p->keep_fp64 = 0;
   p->permute = 1;
@@ -97,9 +95,9 @@ extern "C" pars3_status pars3_get_profile(pars3_matrix *A, pars3_profile *out) {
     P.used[c] = 0;
   }
   out->calls = P.calls;
-  out->ms_inner = ms[0];
-  out->ms_tiles = ms[1];
-  out->ms_far = ms[2];
+  out->ms_band = ms[0];
+  out->ms_fixup = ms[1];
+  out->ms_other = ms[2];
   P.calls = 0;
   return PARS3_OK;
 }
@@ -198,17 +196,14 @@ extern "C" pars3_status pars3_get_split_info(const pars3_matrix *A, pars3_split_
   info->w_in = L.w_in;
   info->t_out = L.t_out;
   info->tile_rows = L.T;
-  info->window_max = L.wmax;
-  info->y_mode = L.y_mode;
   info->value_dtype = L.vdtype;
   info->permute = A->perm_kind;
   info->nnz_inner = A->cnt[0];
   info->nnz_middle = A->cnt[1];
   info->nnz_outer = A->cnt[2];
   info->n_tiles = L.ntiles;
-  info->n_window_tiles = L.n_window_tiles;
-  info->nnz_tiled = L.nnz_tiled;
-  info->nnz_far = L.nnz_far;
+  info->n_blocks = L.nblocks;
+  info->max_blocks = L.max_blocks;
   info->n_components = A->ncomp;
   info->bfs_levels = A->nlevels;
   return PARS3_OK;
@@ -218,51 +213,13 @@ extern "C" pars3_status pars3_get_split_info(const pars3_matrix *A, pars3_split_
 namespace p3 {
 template <class V>
 __global__ void k_collect(const int32_t *__restrict__ prow, const int32_t *__restrict__ pcol,
-                          const int8_t *__restrict__ part, int32_t n, int32_t T, const int32_t *__restrict__ tile_ptr,
-                          const int32_t *__restrict__ tile_alo, const int32_t *__restrict__ tile_la,
-                          const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
-                          const int32_t *__restrict__ far_row, const int32_t *__restrict__ far_col,
-                          const V *__restrict__ far_v, int64_t nfar, const V *__restrict__ in_v, V *__restrict__ out) {
+                          const int32_t *__restrict__ pos_of, int32_t n, const V *__restrict__ ent_v,
+                          const V *__restrict__ in_v, V *__restrict__ out) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int32_t t = i / T, r0 = t * T;
   for (int32_t e = prow[i]; e < prow[i + 1]; e++) {
-    const int32_t j = pcol[e];
-    V v = (V)0;
-    bool found = false;
-    if (part[e] == 0) {
-      v = in_v[(int64_t)(i - j - 1) * n + i];
-      found = true;
-    }
-    if (!found) {
-      const int32_t la = tile_la[t], alo = tile_alo[t];
-      const uint32_t want_slot = j >= r0 ? (uint32_t)(la + (j - r0)) : (uint32_t)(j - alo);
-      const uint32_t key = ((uint32_t)(i - r0) << 16) | want_slot;
-      const bool in_window = j >= r0 || (la > 0 && j >= alo && j < alo + la);
-      if (part[e] == 1 && in_window) {
-        for (int32_t q = tile_ptr[t]; q < tile_ptr[t + 1]; q++)
-          if (ent_rc[q] == key) {
-            v = ent_v[q];
-            found = true;
-            break;
-          }
-      }
-    }
-    if (!found) {
-      // coordinate list is sorted by row: binary search for the row, then scan
-      int64_t lo = 0, hi = nfar;
-      while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (far_row[mid] < i) lo = mid + 1;
-        else hi = mid;
-      }
-      for (int64_t q = lo; q < nfar && far_row[q] == i; q++)
-        if (far_col[q] == j) {
-          v = far_v[q];
-          break;
-        }
-    }
-    out[e] = v;
+    const int32_t q = pos_of[e];
+    out[e] = q >= 0 ? ent_v[q] : in_v[(int64_t)(i - pcol[e] - 1) * n + i];
   }
 }
 }  // namespace p3
@@ -278,17 +235,12 @@ extern "C" pars3_status pars3_get_values(const pars3_matrix *A, int32_t dtype, v
   P3_HIP(out.alloc(A->nnz * elem));
   unsigned g = (unsigned)p3::cdiv(n, 256);
   if (dtype == PARS3_F64 && A->has_f64)
-    p3::k_collect<double><<<g, 256>>>(A->prow.p, A->pcol.p, A->part.p, n, L.T, L.tile_ptr.p, L.tile_alo.p,
-                                      L.tile_la.p, L.ent_rc.p, L.ent_f64.p, L.far_row.p, L.far_col.p, L.far_f64.p,
-                                      L.nnz_far, L.in_f64.p, (double *)out.p);
+    p3::k_collect<double><<<g, 256>>>(A->prow.p, A->pcol.p, L.pos_of.p, n, L.ent_f64.p, L.in_f64.p, (double *)out.p);
   else if (dtype == PARS3_F32 && A->has_f32)
-    p3::k_collect<float><<<g, 256>>>(A->prow.p, A->pcol.p, A->part.p, n, L.T, L.tile_ptr.p, L.tile_alo.p, L.tile_la.p,
-                                     L.ent_rc.p, L.ent_f32.p, L.far_row.p, L.far_col.p, L.far_f32.p, L.nnz_far,
-                                     L.in_f32.p, (float *)out.p);
+    p3::k_collect<float><<<g, 256>>>(A->prow.p, A->pcol.p, L.pos_of.p, n, L.ent_f32.p, L.in_f32.p, (float *)out.p);
   else if (dtype == PARS3_BF16 && A->has_bf16)
-    p3::k_collect<uint16_t><<<g, 256>>>(A->prow.p, A->pcol.p, A->part.p, n, L.T, L.tile_ptr.p, L.tile_alo.p,
-                                        L.tile_la.p, L.ent_rc.p, L.ent_bf16.p, L.far_row.p, L.far_col.p, L.far_bf16.p,
-                                        L.nnz_far, L.in_bf16.p, (uint16_t *)out.p);
+    p3::k_collect<uint16_t><<<g, 256>>>(A->prow.p, A->pcol.p, L.pos_of.p, n, L.ent_bf16.p, L.in_bf16.p,
+                                        (uint16_t *)out.p);
   else
     return fail(PARS3_ESTATE, "get_values: precision %d is not stored", dtype);
   P3_LAUNCHED();

@@ -140,29 +140,29 @@ pars3_status fill_u64(uint64_t *p, uint64_t v, int64_t m, hipStream_t s);
 pars3_status iota_i32(int32_t *p, int64_t m, hipStream_t s);
 
 // ---------------------------------------------------------------- stored layouts
-// One SpMV layout: the three parts of the split arranged for the kernels.
+// One SpMV layout: the three parts of the split arranged for the kernel.
 struct layout {
-  int32_t T = 256, wmax = 1024, y_mode = 0, w_in = 0, t_out = 0;
-  int32_t ntiles = 0, n_window_tiles = 0;
-  int32_t max_slots = 0;  // max over tiles of (back window + tile rows)
-  int64_t nnz_tiled = 0, nnz_far = 0;
+  int32_t T = 256, lgT = 8, w_in = 0, t_out = 0;
+  int32_t ntiles = 0, nblocks = 0, max_blocks = 0;
+  int64_t nnz_blocked = 0;  // middle + outer entries
   int32_t vdtype = PARS3_F64;
   // inner band, diagonal-major: value of (i, i-k) at [(k-1)*n + i]
   dbuf<double> in_f64;
   dbuf<float> in_f32;
   dbuf<uint16_t> in_bf16;
-  // tiles of T rows: entries [tile_ptr[t], tile_ptr[t+1]); back window
-  // columns [tile_alo[t], tile_alo[t] + tile_la[t])
-  dbuf<int32_t> tile_ptr, tile_alo, tile_la;
-  dbuf<uint32_t> ent_rc;  // (row - r0) << 16 | slot
+  // tile-pair blocks: entries [blk_start[b], blk_start[b+1]) of block b, whose
+  // row tile is blk_t[b] and column tile blk_u[b]; entry word
+  // (row - row tile start) << 16 | (column - column tile start)
+  dbuf<uint32_t> ent_rc;
   dbuf<double> ent_f64;
   dbuf<float> ent_f32;
   dbuf<uint16_t> ent_bf16;
-  // coordinate list (outer part plus middle entries outside tile windows)
-  dbuf<int32_t> far_row, far_col;
-  dbuf<double> far_f64;
-  dbuf<float> far_f32;
-  dbuf<uint16_t> far_bf16;
+  dbuf<int32_t> blk_start, blk_t, blk_u;
+  // row tile t owns blocks [tblk_ptr[t], tblk_ptr[t+1]); column tile u is the
+  // column tile of blocks ublk[ublk_ptr[u] .. ublk_ptr[u+1]) (ascending)
+  dbuf<int32_t> tblk_ptr, ublk_ptr, ublk;
+  // layout position of every canonical entry (-1 for inner-band entries)
+  dbuf<int32_t> pos_of;
 };
 
 }  // namespace p3
@@ -208,7 +208,7 @@ pars3_status permute_gpu(pars3_matrix *A, hipStream_t s);
 // layout.hip
 pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipStream_t s);
 // spmv.hip
-enum { PROF_INNER = 0, PROF_TILES = 1, PROF_FAR = 2 };
+enum { PROF_BAND = 0, PROF_FIXUP = 1, PROF_OTHER = 2 };
 pars3_status prof_mark(pars3_matrix *A, int cls, int stop, hipStream_t s);
 pars3_status spmv_rcm(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, hipStream_t s);
 pars3_status gather_rows(const void *src, void *dst, const int32_t *idx, int64_t n, int k, size_t elem,

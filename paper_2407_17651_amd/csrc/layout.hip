@@ -1,19 +1,19 @@
-// Three-way split of the band and the layouts the product kernels read
+// Three-way split of the band and the layout the product kernel reads
 // (Sections 1 and 3.1.2: diagonal/inner, middle and outer parts chosen by
 // distance from the diagonal, the outer distance set by a user bandwidth).
 //
 // For a stored entry (i, j) of the reordered matrix, d = i - j:
-//   inner  d <= w_in         -> diagonal-major band, no indices, read by the
-//                               gather kernel that also applies the shift;
-//   middle w_in < d <= t_out -> row tiles of T rows; a tile keeps in LDS the
-//                               x and y values of its own rows and of one
-//                               contiguous "back" window of columns
-//                               [alo, alo + la) holding its targets j < r0;
-//   outer  d > t_out         -> coordinate list (rows ascending).
-// Middle entries of a tile whose back targets do not fit a window of
-// `window_max` columns also go to the coordinate list, which the kernels treat
-// exactly like the outer part.  Every placement is a stable compaction by a
-// prefix sum in row-major entry order, so the layout is deterministic.
+//   inner  d <= w_in         -> diagonal-major band, no indices;
+//   middle w_in < d <= t_out -> tile-pair blocks;
+//   outer  d > t_out         -> tile-pair blocks of their own.
+// Rows are cut into tiles of T rows.  Entry (i, j) of part p belongs to block
+// (t, p, u) with t = i / T (row tile) and u = j / T (column tile, u <= t).
+// Entries are sorted by (t, p, u, column, row): the blocks of a row tile are
+// contiguous, and inside a block the entries of one column are contiguous.
+// Each entry stores ((i - t*T) << 16 | (j - u*T)) and its value.  Per row
+// tile: its block range; per column tile: the list of blocks whose column tile
+// it is.  All placement is a stable radix sort plus prefix sums, so the layout
+// is deterministic.
 #include <algorithm>
 
 #include "internal.h"
@@ -46,70 +46,25 @@ __global__ __launch_bounds__(TB) void k_classify(const int32_t *__restrict__ ero
   __shared__ unsigned long long bc[3];
   if (threadIdx.x < 3) bc[threadIdx.x] = 0;
   __syncthreads();
-  unsigned long long c[3] = {0, 0, 0};
+  unsigned long long c0 = 0, c1 = 0, c2 = 0;
   for (int64_t e = (int64_t)blockIdx.x * TB + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * TB) {
     int32_t d = erow[e] - pcol[e];
     int8_t p = d <= w_in ? 0 : (d <= t_out ? 1 : 2);
     part[e] = p;
-    c[p]++;
+    c0 += p == 0;
+    c1 += p == 1;
+    c2 += p == 2;
   }
-  for (int q = 0; q < 3; q++) agg_atomic_add<unsigned long long>(bc, q, c[q], true);
+  agg_atomic_add<unsigned long long>(bc, 0, c0, true);
+  agg_atomic_add<unsigned long long>(bc, 1, c1, true);
+  agg_atomic_add<unsigned long long>(bc, 2, c2, true);
   __syncthreads();
   if (threadIdx.x < 3) atomicAdd(&cnt[threadIdx.x], bc[threadIdx.x]);
 }
-// back-window bounds of each tile: columns j < r0 of its middle entries
-__global__ void k_tile_bounds(const int32_t *__restrict__ erow, const int32_t *__restrict__ pcol,
-                              const int8_t *__restrict__ part, int64_t nnz, int32_t T, int32_t *__restrict__ tmin,
-                              int32_t *__restrict__ tmax) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool ok = e < nnz && part[e] == 1;
-  int32_t i = ok ? erow[e] : 0, j = ok ? pcol[e] : 0;
-  int32_t t = i / T, r0 = t * T;
-  ok = ok && j < r0;
-  agg_atomic_min<int32_t>(tmin, t, j, ok, 0x7fffffff);
-  agg_atomic_max<int32_t>(tmax, t, j, ok, -1);
-}
-__global__ void k_tile_window(const int32_t *__restrict__ tmin, const int32_t *__restrict__ tmax, int32_t ntiles,
-                              int32_t wmax, int32_t use_windows, int32_t *__restrict__ alo, int32_t *__restrict__ la) {
-  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntiles) return;
-  int32_t lo = tmin[t], hi = tmax[t];
-  if (use_windows && hi >= lo && hi - lo + 1 <= wmax) {
-    alo[t] = lo;
-    la[t] = hi - lo + 1;
-  } else {
-    alo[t] = 0;
-    la[t] = 0;
-  }
-}
-// placement flags: 1 = tile kernel, 2 = coordinate list, 0 = inner band
-__global__ void k_place(const int32_t *__restrict__ erow, const int32_t *__restrict__ pcol,
-                        const int8_t *__restrict__ part, int64_t nnz, int32_t T, int32_t use_tiles,
-                        const int32_t *__restrict__ la, int32_t *__restrict__ ftile, int32_t *__restrict__ ffar,
-                        int32_t *__restrict__ tcount) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = e < nnz;
-  int32_t i = ok ? erow[e] : 0, j = ok ? pcol[e] : 0;
-  int32_t t = i / T, r0 = t * T;
-  int tiled = 0, far = 0;
-  if (!ok) {
-  } else if (part[e] == 1) {
-    if (use_tiles && (j >= r0 || la[t] > 0)) tiled = 1;
-    else far = 1;
-  } else if (part[e] == 2) {
-    far = 1;
-  }
-  if (ok) {
-    ftile[e] = tiled;
-    ffar[e] = far;
-  }
-  agg_atomic_add<int32_t>(tcount, t, 1, tiled);
-}
 
-template <class F>
 __device__ __forceinline__ void store_vals(int64_t at, double v, double *f64, float *f32, uint16_t *bf16) {
   if (f64) f64[at] = v;
-  float f = (float)v;  // round to nearest even
+  float f = (float)v;  // IEEE round to nearest even
   if (f32) f32[at] = f;
   if (bf16) {
     uint32_t u = __float_as_uint(f);
@@ -120,40 +75,89 @@ __device__ __forceinline__ void store_vals(int64_t at, double v, double *f64, fl
   }
 }
 
-__global__ void k_fill_layout(const int32_t *__restrict__ erow, const int32_t *__restrict__ pcol,
-                              const double *__restrict__ pval, const int8_t *__restrict__ part, int64_t nnz, int32_t n,
-                              int32_t T, const int32_t *__restrict__ alo, const int32_t *__restrict__ la,
-                              const int32_t *__restrict__ ftile, const int32_t *__restrict__ ptile,
-                              const int32_t *__restrict__ ffar, const int32_t *__restrict__ pfar,
-                              uint32_t *__restrict__ ent_rc, double *ef64, float *ef32, uint16_t *ebf16,
-                              int32_t *__restrict__ far_row, int32_t *__restrict__ far_col, double *ff64, float *ff32,
-                              uint16_t *fbf16, double *if64, float *if32, uint16_t *ibf16) {
+// Inner band values go to their diagonal-major slot; block entries get a sort
+// key (t, p, u, column offset, row offset) with the entry index as payload.
+__global__ void k_inner_and_keys(const int32_t *__restrict__ erow, const int32_t *__restrict__ pcol,
+                                 const double *__restrict__ pval, const int8_t *__restrict__ part, int64_t nnz,
+                                 int32_t n, int32_t T, int lgT, int tbits, const int32_t *__restrict__ kpos,
+                                 uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, double *if64, float *if32,
+                                 uint16_t *ibf16) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
-  int32_t i = erow[e], j = pcol[e];
-  double v = pval[e];
-  if (part[e] == 0) {
-    int64_t at = (int64_t)(i - j - 1) * n + i;
-    store_vals<double>(at, v, if64, if32, ibf16);
+  const int32_t i = erow[e], j = pcol[e];
+  const int p = part[e];
+  if (p == 0) {
+    store_vals((int64_t)(i - j - 1) * n + i, pval[e], if64, if32, ibf16);
     return;
   }
-  if (ftile[e]) {
-    int32_t t = i / T, r0 = t * T;
-    int32_t a = la[t];
-    uint32_t slot = j >= r0 ? (uint32_t)(a + (j - r0)) : (uint32_t)(j - alo[t]);
-    int64_t at = ptile[e];
-    ent_rc[at] = ((uint32_t)(i - r0) << 16) | slot;
-    store_vals<double>(at, v, ef64, ef32, ebf16);
-  } else if (ffar[e]) {
-    int64_t at = pfar[e];
-    far_row[at] = i;
-    far_col[at] = j;
-    store_vals<double>(at, v, ff64, ff32, fbf16);
+  const uint64_t t = (uint64_t)(i >> lgT), u = (uint64_t)(j >> lgT);
+  const uint64_t ri = (uint64_t)(i & (T - 1)), cj = (uint64_t)(j & (T - 1));
+  uint64_t key = t;
+  key = (key << 1) | (uint64_t)(p - 1);
+  key = (key << tbits) | u;
+  key = (key << lgT) | cj;
+  key = (key << lgT) | ri;
+  const int32_t at = kpos[e];
+  keys[at] = key;
+  vals[at] = (uint32_t)e;
+}
+__global__ void k_block_flags(const uint64_t *__restrict__ keys, int64_t m, int lgT, int32_t *__restrict__ flag) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const uint64_t b = keys[q] >> (2 * lgT);
+  flag[q] = (q == 0 || (keys[q - 1] >> (2 * lgT)) != b) ? 1 : 0;
+}
+__global__ void k_fill_blocks(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t m, int lgT,
+                              int tbits, const int32_t *__restrict__ flag, const int32_t *__restrict__ bpos,
+                              const double *__restrict__ pval, uint32_t *__restrict__ ent_rc, double *ef64, float *ef32,
+                              uint16_t *ebf16, int32_t *__restrict__ pos_of, int32_t *__restrict__ blk_start,
+                              int32_t *__restrict__ blk_t, int32_t *__restrict__ blk_u,
+                              int32_t *__restrict__ tcount, int32_t *__restrict__ ucount) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const uint64_t k = keys[q];
+  const uint32_t e = vals[q];
+  const uint32_t T1 = (1u << lgT) - 1u;
+  const uint32_t ri = (uint32_t)(k & T1), cj = (uint32_t)((k >> lgT) & T1);
+  ent_rc[q] = (ri << 16) | cj;
+  store_vals(q, pval[e], ef64, ef32, ebf16);
+  pos_of[e] = (int32_t)q;
+  if (flag[q]) {
+    const uint64_t b = k >> (2 * lgT);
+    const int32_t u = (int32_t)(b & ((1ull << tbits) - 1ull));
+    const int32_t t = (int32_t)(b >> (tbits + 1));
+    const int32_t id = bpos[q];
+    blk_start[id] = (int32_t)q;
+    blk_t[id] = t;
+    blk_u[id] = u;
+    atomicAdd(&tcount[t], 1);
+    atomicAdd(&ucount[u], 1);
   }
 }
-__global__ void k_max_slots(const int32_t *__restrict__ la, int32_t ntiles, int32_t T, int32_t *__restrict__ mx) {
-  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < ntiles) atomicMax(mx, la[t] + T);
+__global__ void k_ulist_fill(const int32_t *__restrict__ blk_u, int32_t nb, const int32_t *__restrict__ uptr,
+                             int32_t *__restrict__ fill, int32_t *__restrict__ tmp) {
+  int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) tmp[uptr[blk_u[b]] + atomicAdd(&fill[blk_u[b]], 1)] = b;
+}
+// sort each list by its values (distinct): destination = rank in the list
+__global__ void k_list_sort(const int32_t *__restrict__ ptr, int32_t nlists, const int32_t *__restrict__ in, int64_t m,
+                            int32_t *__restrict__ out) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  int32_t lo = 0, hi = nlists - 1;  // the list that owns q
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  const int32_t v = in[q];
+  int32_t rank = 0;
+  for (int32_t r = ptr[lo]; r < ptr[lo + 1]; r++) rank += in[r] < v;
+  out[ptr[lo] + rank] = v;
+}
+__global__ void k_pos_prefix(const int8_t *__restrict__ part, int64_t nnz, int32_t *__restrict__ flag) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) flag[e] = part[e] != 0;
 }
 
 pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipStream_t s) {
@@ -176,17 +180,15 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   int32_t beta = 0;
   P3_HIP(hipMemcpyAsync(&beta, dbeta.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   P3_HIP(hipStreamSynchronize(s));
-  int32_t w_in = p.w_in < 0 ? 0 : p.w_in;
-  int32_t t_out = p.t_out < 0 ? std::max(beta - 3, 0) : p.t_out;
+  const int32_t w_in = p.w_in < 0 ? 0 : p.w_in;
+  const int32_t t_out = p.t_out < 0 ? std::max(beta - 3, 0) : p.t_out;
   if (w_in > t_out) return fail(PARS3_EINVAL, "split: w_in (%d) > t_out (%d)", w_in, t_out);
-  int32_t T = p.tile_rows <= 0 ? 256 : p.tile_rows;
-  int32_t wmax = p.window_max <= 0 ? 1024 : p.window_max;
+  const int32_t T = p.tile_rows <= 0 ? 256 : p.tile_rows;
   if (T != 64 && T != 128 && T != 256 && T != 512 && T != 1024)
     return fail(PARS3_EINVAL, "split: tile_rows must be 64, 128, 256, 512 or 1024 (got %d)", T);
-  if (wmax > 16384) return fail(PARS3_EINVAL, "split: window_max must be <= 16384 (got %d)", wmax);
   if (w_in > 64) return fail(PARS3_EINVAL, "split: w_in must be <= 64 (got %d)", w_in);
   if (p.value_dtype < PARS3_F64 || p.value_dtype > PARS3_BF16) return fail(PARS3_EINVAL, "split: bad value dtype");
-  if (p.y_mode < PARS3_Y_AUTO || p.y_mode > PARS3_Y_ATOMIC) return fail(PARS3_EINVAL, "split: bad y_mode");
+  const int lgT = bits_for((uint64_t)T) - 1;
 
   P3_HIP(A->part.alloc(nnz));
   dbuf<unsigned long long> dcnt;
@@ -200,51 +202,9 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   unsigned long long hc[3] = {0, 0, 0};
   P3_HIP(hipMemcpyAsync(hc, dcnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
   P3_HIP(hipStreamSynchronize(s));
+  const int64_t m = (int64_t)(hc[1] + hc[2]);  // block entries
 
-  // ---- tiles and windows
-  const int32_t ntiles = (int32_t)cdiv(n, T);
-  const int use_tiles = p.y_mode != PARS3_Y_ATOMIC;
-  dbuf<int32_t> tmin, tmax, tcount, ftile, ffar, ptile, pfar, mx;
-  P3_HIP(L.tile_alo.alloc(ntiles));
-  P3_HIP(L.tile_la.alloc(ntiles));
-  P3_HIP(L.tile_ptr.alloc(ntiles + 1));
-  P3_HIP(tmin.alloc(ntiles));
-  P3_HIP(tmax.alloc(ntiles));
-  P3_HIP(tcount.alloc(ntiles));
-  P3_HIP(ftile.alloc(nnz));
-  P3_HIP(ffar.alloc(nnz));
-  P3_HIP(ptile.alloc(nnz + 1));
-  P3_HIP(pfar.alloc(nnz + 1));
-  P3_HIP(mx.alloc(1));
-  P3_TRY(fill_i32(tmin.p, 0x7fffffff, ntiles, s));
-  P3_TRY(fill_i32(tmax.p, -1, ntiles, s));
-  P3_HIP(hipMemsetAsync(tcount.p, 0, std::max<int64_t>(ntiles, 1) * sizeof(int32_t), s));
-  P3_HIP(hipMemsetAsync(mx.p, 0, sizeof(int32_t), s));
-  if (nnz > 0) {
-    k_tile_bounds<<<nblk(nnz), TB, 0, s>>>(erow.p, A->pcol.p, A->part.p, nnz, T, tmin.p, tmax.p);
-    P3_LAUNCHED();
-  }
-  if (ntiles > 0) {
-    k_tile_window<<<nblk(ntiles), TB, 0, s>>>(tmin.p, tmax.p, ntiles, wmax, use_tiles, L.tile_alo.p, L.tile_la.p);
-    P3_LAUNCHED();
-    k_max_slots<<<nblk(ntiles), TB, 0, s>>>(L.tile_la.p, ntiles, T, mx.p);
-    P3_LAUNCHED();
-  }
-  if (nnz > 0) {
-    k_place<<<nblk(nnz), TB, 0, s>>>(erow.p, A->pcol.p, A->part.p, nnz, T, use_tiles, L.tile_la.p, ftile.p, ffar.p,
-                                     tcount.p);
-    P3_LAUNCHED();
-  }
-  P3_TRY(scan_i32(ftile.p, ptile.p, nnz, s));
-  P3_TRY(scan_i32(ffar.p, pfar.p, nnz, s));
-  P3_TRY(scan_i32(tcount.p, L.tile_ptr.p, ntiles, s));
-  int32_t ntiled = 0, nfar = 0, maxslots = 0;
-  P3_HIP(hipMemcpyAsync(&ntiled, ptile.p + nnz, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  P3_HIP(hipMemcpyAsync(&nfar, pfar.p + nnz, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  P3_HIP(hipMemcpyAsync(&maxslots, mx.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  P3_HIP(hipStreamSynchronize(s));
-
-  // ---- values of the stored precisions
+  // ---- value arrays of the stored precisions
   const int vd = p.value_dtype;
   const bool want64 = vd == PARS3_F64 || p.keep_fp64;
   const bool want32 = vd == PARS3_F32;
@@ -255,57 +215,118 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   L.ent_f64.release();
   L.ent_f32.release();
   L.ent_bf16.release();
-  L.far_f64.release();
-  L.far_f32.release();
-  L.far_bf16.release();
   const int64_t nin = (int64_t)w_in * n;
   if (want64) {
     P3_HIP(L.in_f64.alloc(nin));
-    P3_HIP(L.ent_f64.alloc(ntiled));
-    P3_HIP(L.far_f64.alloc(nfar));
+    P3_HIP(L.ent_f64.alloc(m));
     if (nin) P3_HIP(hipMemsetAsync(L.in_f64.p, 0, nin * sizeof(double), s));
   }
   if (want32) {
     P3_HIP(L.in_f32.alloc(nin));
-    P3_HIP(L.ent_f32.alloc(ntiled));
-    P3_HIP(L.far_f32.alloc(nfar));
+    P3_HIP(L.ent_f32.alloc(m));
     if (nin) P3_HIP(hipMemsetAsync(L.in_f32.p, 0, nin * sizeof(float), s));
   }
   if (want16) {
     P3_HIP(L.in_bf16.alloc(nin));
-    P3_HIP(L.ent_bf16.alloc(ntiled));
-    P3_HIP(L.far_bf16.alloc(nfar));
+    P3_HIP(L.ent_bf16.alloc(m));
     if (nin) P3_HIP(hipMemsetAsync(L.in_bf16.p, 0, nin * sizeof(uint16_t), s));
   }
-  P3_HIP(L.ent_rc.alloc(ntiled));
-  P3_HIP(L.far_row.alloc(nfar));
-  P3_HIP(L.far_col.alloc(nfar));
+
+  // ---- block entries: sort keys (t, p, u, column, row)
+  const int32_t ntiles = (int32_t)cdiv(n, T);
+  const int tbits = std::max(1, bits_for((uint64_t)std::max(ntiles - 1, 0)));
+  const int key_bits = 2 * tbits + 1 + 2 * lgT;
+  if (key_bits > 64) return fail(PARS3_EINVAL, "split: matrix too large for the block key (%d bits)", key_bits);
+  dbuf<int32_t> kflag, kpos;
+  dbuf<uint64_t> k0, k1;
+  dbuf<uint32_t> v0, v1;
+  P3_HIP(kflag.alloc(nnz));
+  P3_HIP(kpos.alloc(nnz + 1));
+  P3_HIP(k0.alloc(m));
+  P3_HIP(k1.alloc(m));
+  P3_HIP(v0.alloc(m));
+  P3_HIP(v1.alloc(m));
   if (nnz > 0) {
-    k_fill_layout<<<nblk(nnz), TB, 0, s>>>(
-        erow.p, A->pcol.p, A->pval.p, A->part.p, nnz, n, T, L.tile_alo.p, L.tile_la.p, ftile.p, ptile.p, ffar.p,
-        pfar.p, L.ent_rc.p, want64 ? L.ent_f64.p : nullptr, want32 ? L.ent_f32.p : nullptr,
-        want16 ? L.ent_bf16.p : nullptr, L.far_row.p, L.far_col.p, want64 ? L.far_f64.p : nullptr,
-        want32 ? L.far_f32.p : nullptr, want16 ? L.far_bf16.p : nullptr, want64 ? L.in_f64.p : nullptr,
-        want32 ? L.in_f32.p : nullptr, want16 ? L.in_bf16.p : nullptr);
+    k_pos_prefix<<<nblk(nnz), TB, 0, s>>>(A->part.p, nnz, kflag.p);
     P3_LAUNCHED();
   }
-  // window tiles (for the read-back)
-  std::vector<int32_t> hla(ntiles);
-  if (ntiles) P3_HIP(hipMemcpyAsync(hla.data(), L.tile_la.p, ntiles * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  P3_TRY(scan_i32(kflag.p, kpos.p, nnz, s));
+  if (nnz > 0) {
+    k_inner_and_keys<<<nblk(nnz), TB, 0, s>>>(erow.p, A->pcol.p, A->pval.p, A->part.p, nnz, n, T, lgT, tbits, kpos.p,
+                                              k0.p, v0.p, want64 ? L.in_f64.p : nullptr,
+                                              want32 ? L.in_f32.p : nullptr, want16 ? L.in_bf16.p : nullptr);
+    P3_LAUNCHED();
+  }
+  P3_TRY(radix_sort_pairs(k0.p, v0.p, k1.p, v1.p, m, key_bits, s));
+  k1.release();
+  v1.release();
+
+  // ---- blocks
+  dbuf<int32_t> bflag, bpos, tcount, ucount;
+  P3_HIP(bflag.alloc(m));
+  P3_HIP(bpos.alloc(m + 1));
+  P3_HIP(tcount.alloc(ntiles));
+  P3_HIP(ucount.alloc(ntiles));
+  if (m > 0) {
+    k_block_flags<<<nblk(m), TB, 0, s>>>(k0.p, m, lgT, bflag.p);
+    P3_LAUNCHED();
+  }
+  P3_TRY(scan_i32(bflag.p, bpos.p, m, s));
+  int32_t nb = 0;
+  P3_HIP(hipMemcpyAsync(&nb, bpos.p + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   P3_HIP(hipStreamSynchronize(s));
-  int32_t nwin = 0;
-  for (int32_t t = 0; t < ntiles; t++) nwin += hla[t] > 0;
+  const int32_t m32 = (int32_t)m;
+  P3_HIP(L.ent_rc.alloc(m));
+  P3_HIP(L.pos_of.alloc(nnz));
+  P3_HIP(L.blk_start.alloc(nb + 1));
+  P3_HIP(L.blk_t.alloc(nb));
+  P3_HIP(L.blk_u.alloc(nb));
+  P3_HIP(L.tblk_ptr.alloc(ntiles + 1));
+  P3_HIP(L.ublk_ptr.alloc(ntiles + 1));
+  P3_HIP(L.ublk.alloc(nb));
+  if (ntiles > 0) {
+    P3_HIP(hipMemsetAsync(tcount.p, 0, ntiles * sizeof(int32_t), s));
+    P3_HIP(hipMemsetAsync(ucount.p, 0, ntiles * sizeof(int32_t), s));
+  }
+  P3_HIP(hipMemcpyAsync(L.blk_start.p + nb, &m32, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (nnz > 0) P3_TRY(fill_i32(L.pos_of.p, -1, nnz, s));
+  if (m > 0) {
+    k_fill_blocks<<<nblk(m), TB, 0, s>>>(k0.p, v0.p, m, lgT, tbits, bflag.p, bpos.p, A->pval.p, L.ent_rc.p,
+                                         want64 ? L.ent_f64.p : nullptr, want32 ? L.ent_f32.p : nullptr,
+                                         want16 ? L.ent_bf16.p : nullptr, L.pos_of.p, L.blk_start.p, L.blk_t.p,
+                                         L.blk_u.p, tcount.p, ucount.p);
+    P3_LAUNCHED();
+  }
+  P3_TRY(scan_i32(tcount.p, L.tblk_ptr.p, ntiles, s));
+  P3_TRY(scan_i32(ucount.p, L.ublk_ptr.p, ntiles, s));
+  if (nb > 0) {
+    dbuf<int32_t> fill, tmp;
+    P3_HIP(fill.alloc(ntiles));
+    P3_HIP(tmp.alloc(nb));
+    P3_HIP(hipMemsetAsync(fill.p, 0, ntiles * sizeof(int32_t), s));
+    k_ulist_fill<<<nblk(nb), TB, 0, s>>>(L.blk_u.p, nb, L.ublk_ptr.p, fill.p, tmp.p);
+    P3_LAUNCHED();
+    k_list_sort<<<nblk(nb), TB, 0, s>>>(L.ublk_ptr.p, ntiles, tmp.p, nb, L.ublk.p);
+    P3_LAUNCHED();
+  }
+  // per-tile maxima of blocks (row side and column side), for the read-back
+  std::vector<int32_t> ht(ntiles + 1), hu(ntiles + 1);
+  if (ntiles) {
+    P3_HIP(hipMemcpyAsync(ht.data(), L.tblk_ptr.p, (ntiles + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P3_HIP(hipMemcpyAsync(hu.data(), L.ublk_ptr.p, (ntiles + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
+  P3_HIP(hipStreamSynchronize(s));
+  int32_t maxb = 0;
+  for (int32_t t = 0; t < ntiles; t++) maxb = std::max(maxb, std::max(ht[t + 1] - ht[t], hu[t + 1] - hu[t]));
 
   L.T = T;
-  L.wmax = wmax;
-  L.y_mode = p.y_mode;
+  L.lgT = lgT;
   L.w_in = w_in;
   L.t_out = t_out;
   L.ntiles = ntiles;
-  L.n_window_tiles = nwin;
-  L.max_slots = maxslots;
-  L.nnz_tiled = ntiled;
-  L.nnz_far = nfar;
+  L.nblocks = nb;
+  L.max_blocks = maxb;
+  L.nnz_blocked = m;
   L.vdtype = vd;
   A->beta = beta;
   A->cnt[0] = (int64_t)hc[0];
@@ -318,7 +339,6 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   A->params.w_in = w_in;
   A->params.t_out = t_out;
   A->params.tile_rows = T;
-  A->params.window_max = wmax;
   return PARS3_OK;
 }
 

@@ -1,20 +1,22 @@
 // Skew-symmetric product y = shift*x + S*x, S = L - L^T, from the stored
-// lower triangle only: every stored l_ij is read once and gives the two
-// products y_i += l_ij x_j and y_j -= l_ij x_i (eqs. (2)-(6), Section 3.1.2).
+// lower triangle only (eqs. (2)-(6), Section 3.1.2): every stored l_ij stands
+// for the pair y_i += l_ij x_j and y_j -= l_ij x_i.
 //
-// Launch sequence on one stream (each kernel's writes are visible to the next):
-//  1. k_inner : one thread per row.  y_i = shift*x_i plus the whole inner-band
-//     contribution, gathered from the diagonal-major band in both directions
-//     (the row's own entries and the entries of the rows below that store
-//     column i), so no atomics are needed.  This is the only writer of y that
-//     does not add, so it also initialises y.
-//  2. k_tiles : one workgroup per tile of T rows.  The tile's entries are
-//     prefetched into registers, then the x values of the tile's rows and of
-//     its back window are staged in LDS; both products of every middle entry
-//     accumulate into LDS (ds_add); the tile then adds its LDS sums to y with
-//     one global atomic per touched row (consecutive addresses).  Extra
-//     workgroups of the same launch take the coordinate list (the outer part
-//     and middle entries outside any window), both products by global atomics.
+// One launch, one workgroup per tile of T rows, no global atomics and one
+// plain store per output row.  The entries are stored once, grouped in
+// tile-pair blocks (row tile t, column tile u).  The workgroup of tile t
+// gathers into LDS (ds_add) every product that lands in its rows:
+//   row side    : blocks (t, u) for all u      -> y_i += l_ij x_j, i in t;
+//   column side : blocks (t', t) for all t'    -> y_j -= l_ij x_i, j in t;
+// then writes y_i = shift*x_i + inner band (gathered per row in both
+// directions from its diagonal-major store) + LDS sum.  The block (t', t)
+// is thus read by two workgroups, t' and t.  In the banded reordered matrix
+// t' - t stays within about beta/T tiles; tiles run in ascending order inside
+// each XCD (see xcd_tile), so the second read of a block finds it in that
+// XCD's L2 and the matrix crosses HBM about once: the transfer saving of
+// storing one triangle (Section 3) is kept, while the exchange of conflicting
+// products between owners of different rows (Section 3.1.2) becomes a read of
+// shared data instead of a remote accumulation.
 // Values are FP64, FP32 or BF16; vectors and accumulation are FP64 for FP64
 // values and FP32 otherwise.  k right-hand sides are stored row-major.
 #include <algorithm>
@@ -25,190 +27,180 @@ namespace p3 {
 
 static constexpr int TB = 256;
 static constexpr int LDS_MAX = 160 * 1024;
+static constexpr int SEGS = 64;  // segments (blocks) staged per round
+static constexpr int PRE = 4;    // entries per thread whose loads are issued together
 
 template <class V>
 struct vload;
 template <>
 struct vload<double> {
-  static __device__ __forceinline__ double get(const double *p, int64_t i) { return __builtin_nontemporal_load(p + i); }
+  static __device__ __forceinline__ double nt(const double *p, int64_t i) { return __builtin_nontemporal_load(p + i); }
+  static __device__ __forceinline__ double ld(const double *p, int64_t i) { return p[i]; }
 };
 template <>
 struct vload<float> {
-  static __device__ __forceinline__ float get(const float *p, int64_t i) { return __builtin_nontemporal_load(p + i); }
+  static __device__ __forceinline__ float nt(const float *p, int64_t i) { return __builtin_nontemporal_load(p + i); }
+  static __device__ __forceinline__ float ld(const float *p, int64_t i) { return p[i]; }
 };
 template <>
 struct vload<uint16_t> {
-  static __device__ __forceinline__ float get(const uint16_t *p, int64_t i) {
+  static __device__ __forceinline__ float nt(const uint16_t *p, int64_t i) {
     return __uint_as_float((uint32_t)__builtin_nontemporal_load(p + i) << 16);
   }
+  static __device__ __forceinline__ float ld(const uint16_t *p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
 };
 
-template <class V, class X, int K>
-__global__ __launch_bounds__(TB) void k_inner(const V *__restrict__ dia, int32_t w_in, int32_t n, X shift,
-                                              const X *__restrict__ x, X *__restrict__ y) {
-  const int32_t i = blockIdx.x * TB + threadIdx.x;
-  if (i >= n) return;
-  X acc[K];
-#pragma unroll
-  for (int c = 0; c < K; c++) acc[c] = shift * x[(int64_t)i * K + c];
-  for (int32_t k = 1; k <= w_in; k++) {
-    const int64_t base = (int64_t)(k - 1) * n;
-    if (i - k >= 0) {
-      X l = (X)vload<V>::get(dia, base + i);
-      if (l != (X)0) {
-#pragma unroll
-        for (int c = 0; c < K; c++) acc[c] += l * x[(int64_t)(i - k) * K + c];
-      }
-    }
-    if (i + k < n) {
-      X l = (X)vload<V>::get(dia, base + i + k);
-      if (l != (X)0) {
-#pragma unroll
-        for (int c = 0; c < K; c++) acc[c] -= l * x[(int64_t)(i + k) * K + c];
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < K; c++) y[(int64_t)i * K + c] = acc[c];
-}
-
-// Entries prefetched into registers per thread before the x window is staged,
-// so that the matrix stream is in flight while the window loads.
-static constexpr int PRE = 4;
-// Coordinate-list entries per thread in the extra workgroups of the launch.
-static constexpr int FAR_ITEMS = 8;
-
-template <class X, int K>
-__device__ __forceinline__ void tile_entry(uint32_t rc, X v, int32_t la, const X *xs, X *ys) {
-  const int32_t si = la + (int32_t)(rc >> 16), sj = (int32_t)(rc & 0xffffu);
-#pragma unroll
-  for (int c = 0; c < K; c++) {
-    const X xi = xs[si * K + c], xj = xs[sj * K + c];
-    atomicAdd(&ys[si * K + c], v * xj);
-    atomicAdd(&ys[sj * K + c], -(v * xi));
-  }
-}
-
-// Workgroups [0, tile_grid) process tiles; the remaining ones process the
-// coordinate list, FAR_ITEMS entries per thread.
-template <class V, class X, int K>
-__global__ __launch_bounds__(TB) void k_tiles(const int32_t *__restrict__ tile_ptr, const int32_t *__restrict__ tile_alo,
-                                              const int32_t *__restrict__ tile_la, const uint32_t *__restrict__ ent_rc,
-                                              const V *__restrict__ ent_v, int32_t ntiles, int32_t T, int32_t n,
-                                              int32_t tile_grid, const int32_t *__restrict__ far_row,
-                                              const int32_t *__restrict__ far_col, const V *__restrict__ far_v,
-                                              int64_t nfar, const X *__restrict__ x, X *__restrict__ y) {
-  extern __shared__ unsigned char smem[];
-  const int32_t b = blockIdx.x;
-  if (b >= tile_grid) {
-    const int64_t base = (int64_t)(b - tile_grid) * TB * FAR_ITEMS + threadIdx.x;
-#pragma unroll
-    for (int q = 0; q < FAR_ITEMS; q++) {
-      const int64_t e = base + (int64_t)q * TB;
-      if (e >= nfar) break;
-      const int32_t i = far_row[e], j = far_col[e];
-      const X v = (X)vload<V>::get(far_v, e);
-#pragma unroll
-      for (int c = 0; c < K; c++) {
-        const X xi = x[(int64_t)i * K + c], xj = x[(int64_t)j * K + c];
-        unsafeAtomicAdd(&y[(int64_t)i * K + c], v * xj);
-        unsafeAtomicAdd(&y[(int64_t)j * K + c], -(v * xi));
-      }
-    }
-    return;
-  }
-  // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
-  // contiguous range of tiles so that its L2 keeps the x and y lines that the
-  // back windows of its later tiles revisit.
+// Workgroups are dispatched round-robin over the 8 XCDs: block b runs on XCD
+// b % 8.  Give every XCD a contiguous range of tiles, taken in ascending order.
+__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
   const int32_t per = (ntiles + 7) >> 3;
-  const int32_t t = (b & 7) * per + (b >> 3);
+  return (b & 7) * per + (b >> 3);
+}
+
+template <class V, class X, int K>
+__global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tblk_ptr, const int32_t *__restrict__ ublk_ptr,
+                                             const int32_t *__restrict__ ublk, const int32_t *__restrict__ blk_start,
+                                             const int32_t *__restrict__ blk_t, const int32_t *__restrict__ blk_u,
+                                             const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
+                                             const V *__restrict__ dia, int32_t w_in, int32_t ntiles, int32_t lgT,
+                                             int32_t n, X shift, const X *__restrict__ x, X *__restrict__ y) {
+  __shared__ int32_t s_start[SEGS], s_pre[SEGS + 1], s_other[SEGS];
+  extern __shared__ unsigned char smem[];
+  X *ys = reinterpret_cast<X *>(smem);
+  const int32_t t = xcd_tile(blockIdx.x, ntiles);
   if (t >= ntiles) return;
-  const int32_t e0 = tile_ptr[t], e1 = tile_ptr[t + 1];
-  if (e0 == e1) return;
-  uint32_t prc[PRE];
-  X pv[PRE];
+  const int32_t r0 = t << lgT;
+  const int32_t rows = min(1 << lgT, n - r0);
+  const int32_t rb0 = tblk_ptr[t], nrow_seg = tblk_ptr[t + 1] - rb0;
+  const int32_t cb0 = ublk_ptr[t], ncol_seg = ublk_ptr[t + 1] - cb0;
+  const int32_t nseg = nrow_seg + ncol_seg;
+  for (int32_t s = threadIdx.x; s < rows * K; s += TB) ys[s] = (X)0;
+  for (int32_t c0 = 0; c0 < nseg; c0 += SEGS) {
+    // stage up to SEGS segments: row-side blocks first, then column-side ones
+    const int32_t cnt = min(SEGS, nseg - c0);
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      int32_t len = 0;
+      if (lane < cnt) {
+        const int32_t g = c0 + lane;
+        const bool row_side = g < nrow_seg;
+        const int32_t b = row_side ? rb0 + g : ublk[cb0 + (g - nrow_seg)];
+        s_start[lane] = blk_start[b];
+        len = blk_start[b + 1] - blk_start[b];
+        // the other tile, negated for the column side
+        s_other[lane] = row_side ? blk_u[b] : -1 - blk_t[b];
+      }
+      int32_t incl = len;
 #pragma unroll
-  for (int q = 0; q < PRE; q++) {
-    const int32_t e = e0 + threadIdx.x + q * TB;
-    prc[q] = 0u;
-    pv[q] = (X)0;
-    if (e < e1) {
-      prc[q] = __builtin_nontemporal_load(ent_rc + e);
-      pv[q] = (X)vload<V>::get(ent_v, e);
+      for (int d = 1; d < 64; d <<= 1) {
+        const int32_t u = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += u;
+      }
+      s_pre[lane + 1] = incl;
+      if (lane == 0) s_pre[0] = 0;
     }
+    __syncthreads();
+    const int32_t total = s_pre[cnt];
+    for (int32_t base = 0; base < total; base += PRE * TB) {
+      int32_t slot[PRE], xrow[PRE];
+      X coef[PRE], xv[PRE][K];
+#pragma unroll
+      for (int q = 0; q < PRE; q++) {
+        const int32_t v = base + q * TB + (int32_t)threadIdx.x;
+        slot[q] = -1;
+        xrow[q] = 0;
+        coef[q] = (X)0;
+        if (v < total) {
+          int32_t lo = 0, hi = cnt - 1;  // segment holding v
+          while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= v) lo = mid;
+            else hi = mid - 1;
+          }
+          const int64_t e = (int64_t)s_start[lo] + (v - s_pre[lo]);
+          const int32_t other = s_other[lo];
+          // row side: last use of the block (nontemporal); column side: first
+          // use, keep it in L2 for the row tile that reads it later
+          const uint32_t rc = other >= 0 ? __builtin_nontemporal_load(ent_rc + e) : ent_rc[e];
+          const X val = other >= 0 ? (X)vload<V>::nt(ent_v, e) : (X)vload<V>::ld(ent_v, e);
+          const int32_t ri = (int32_t)(rc >> 16), cj = (int32_t)(rc & 0xffffu);
+          if (other >= 0) {
+            slot[q] = ri;
+            xrow[q] = (other << lgT) + cj;
+            coef[q] = val;
+          } else {
+            slot[q] = cj;
+            xrow[q] = ((-1 - other) << lgT) + ri;
+            coef[q] = -val;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PRE; q++)
+#pragma unroll
+        for (int c = 0; c < K; c++) xv[q][c] = slot[q] >= 0 ? x[(int64_t)xrow[q] * K + c] : (X)0;
+#pragma unroll
+      for (int q = 0; q < PRE; q++)
+        if (slot[q] >= 0) {
+#pragma unroll
+          for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * K + c], coef[q] * xv[q][c]);
+        }
+    }
+    __syncthreads();  // the segment table is rewritten by the next round
   }
-  const int32_t la = tile_la[t], alo = tile_alo[t], r0 = t * T;
-  const int32_t nslot = la + T;
-  X *xs = reinterpret_cast<X *>(smem);
-  X *ys = xs + (int64_t)nslot * K;
-  for (int32_t s = threadIdx.x; s < nslot; s += TB) {
-    const int32_t row = s < la ? alo + s : r0 + (s - la);
+  if (nseg == 0) __syncthreads();
+  for (int32_t r = threadIdx.x; r < rows; r += TB) {
+    const int64_t i = r0 + r;
+    X acc[K];
 #pragma unroll
-    for (int c = 0; c < K; c++) {
-      xs[s * K + c] = row < n ? x[(int64_t)row * K + c] : (X)0;
-      ys[s * K + c] = (X)0;
+    for (int c = 0; c < K; c++) acc[c] = shift * x[i * K + c] + ys[r * K + c];
+    for (int32_t k = 1; k <= w_in; k++) {
+      const int64_t bse = (int64_t)(k - 1) * n;
+      if (i - k >= 0) {
+        const X l = (X)vload<V>::nt(dia, bse + i);
+        if (l != (X)0) {
+#pragma unroll
+          for (int c = 0; c < K; c++) acc[c] += l * x[(i - k) * K + c];
+        }
+      }
+      if (i + k < n) {
+        const X l = (X)vload<V>::nt(dia, bse + i + k);
+        if (l != (X)0) {
+#pragma unroll
+          for (int c = 0; c < K; c++) acc[c] -= l * x[(i + k) * K + c];
+        }
+      }
     }
-  }
-  __syncthreads();
 #pragma unroll
-  for (int q = 0; q < PRE; q++)
-    if (e0 + (int32_t)threadIdx.x + q * TB < e1) tile_entry<X, K>(prc[q], pv[q], la, xs, ys);
-  for (int32_t e = e0 + threadIdx.x + PRE * TB; e < e1; e += TB)
-    tile_entry<X, K>(__builtin_nontemporal_load(ent_rc + e), (X)vload<V>::get(ent_v, e), la, xs, ys);
-  __syncthreads();
-  for (int32_t s = threadIdx.x; s < nslot; s += TB) {
-    const int32_t row = s < la ? alo + s : r0 + (s - la);
-    if (row >= n) continue;
-#pragma unroll
-    for (int c = 0; c < K; c++) {
-      const X a = ys[s * K + c];
-      if (a != (X)0) unsafeAtomicAdd(&y[(int64_t)row * K + c], a);
-    }
+    for (int c = 0; c < K; c++) y[i * K + c] = acc[c];
   }
 }
 
 template <class V, class X, int K>
-static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, const V *far_v, X shift, const X *x, X *y,
-                           hipStream_t s) {
+static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shift, const X *x, X *y, hipStream_t s) {
   const layout &L = A->lay;
   const int32_t n = (int32_t)A->n;
   if (n == 0) return PARS3_OK;
-  P3_TRY(prof_mark(A, PROF_INNER, 0, s));
-  k_inner<V, X, K><<<(unsigned)cdiv(n, TB), TB, 0, s>>>(in_v, L.w_in, n, shift, x, y);
+  const size_t lds = (size_t)L.T * K * sizeof(X);
+  const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
+  P3_TRY(prof_mark(A, PROF_BAND, 0, s));
+  k_pair<V, X, K><<<grid, TB, lds, s>>>(L.tblk_ptr.p, L.ublk_ptr.p, L.ublk.p, L.blk_start.p, L.blk_t.p, L.blk_u.p,
+                                        L.ent_rc.p, ent_v, in_v, L.w_in, L.ntiles, L.lgT, n, shift, x, y);
   P3_LAUNCHED();
-  P3_TRY(prof_mark(A, PROF_INNER, 1, s));
-  if (L.nnz_tiled + L.nnz_far > 0) {
-    const size_t lds = L.nnz_tiled > 0 ? (size_t)L.max_slots * K * 2 * sizeof(X) : 0;
-    if (lds > (size_t)LDS_MAX)
-      return fail(PARS3_EINVAL, "spmv: a tile needs %zu bytes of LDS for k=%d; reorder with a smaller window_max", lds,
-                  K);
-    static bool attr_set = false;
-    if (!attr_set) {
-      P3_HIP(hipFuncSetAttribute((const void *)k_tiles<V, X, K>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX));
-      attr_set = true;
-    }
-    const int32_t tile_grid = L.nnz_tiled > 0 ? (int32_t)(8 * cdiv(L.ntiles, 8)) : 0;
-    const int64_t far_grid = cdiv(L.nnz_far, (int64_t)TB * FAR_ITEMS);
-    P3_TRY(prof_mark(A, PROF_TILES, 0, s));
-    k_tiles<V, X, K><<<(unsigned)(tile_grid + far_grid), TB, lds, s>>>(
-        L.tile_ptr.p, L.tile_alo.p, L.tile_la.p, L.ent_rc.p, ent_v, L.ntiles, L.T, n, tile_grid, L.far_row.p,
-        L.far_col.p, far_v, L.nnz_far, x, y);
-    P3_LAUNCHED();
-    P3_TRY(prof_mark(A, PROF_TILES, 1, s));
-  }
+  P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;
 }
 
 template <class V, class X>
-static pars3_status dispatch_k(pars3_matrix *A, const V *in_v, const V *ent_v, const V *far_v, double shift,
-                               const void *x, void *y, int k, hipStream_t s) {
+static pars3_status dispatch_k(pars3_matrix *A, const V *in_v, const V *ent_v, double shift, const void *x, void *y,
+                               int k, hipStream_t s) {
   const X *xx = (const X *)x;
   X *yy = (X *)y;
   switch (k) {
-    case 1: return launch<V, X, 1>(A, in_v, ent_v, far_v, (X)shift, xx, yy, s);
-    case 2: return launch<V, X, 2>(A, in_v, ent_v, far_v, (X)shift, xx, yy, s);
-    case 4: return launch<V, X, 4>(A, in_v, ent_v, far_v, (X)shift, xx, yy, s);
-    case 8: return launch<V, X, 8>(A, in_v, ent_v, far_v, (X)shift, xx, yy, s);
+    case 1: return launch<V, X, 1>(A, in_v, ent_v, (X)shift, xx, yy, s);
+    case 2: return launch<V, X, 2>(A, in_v, ent_v, (X)shift, xx, yy, s);
+    case 4: return launch<V, X, 4>(A, in_v, ent_v, (X)shift, xx, yy, s);
+    case 8: return launch<V, X, 8>(A, in_v, ent_v, (X)shift, xx, yy, s);
     default: return fail(PARS3_EINVAL, "spmv: k must be 1, 2, 4 or 8 (got %d)", k);
   }
 }
@@ -238,12 +230,12 @@ pars3_status spmv_rcm(pars3_matrix *A, double shift, const void *x, void *y, int
   if (A->prof.on && A->prof.calls < PROF_MAX) A->prof.calls++;
   if (vec_dtype == PARS3_F64) {
     if (!A->has_f64) return fail(PARS3_ESTATE, "spmv: FP64 values are not stored (value_dtype/keep_fp64)");
-    return dispatch_k<double, double>(A, L.in_f64.p, L.ent_f64.p, L.far_f64.p, shift, x, y, k, s);
+    return dispatch_k<double, double>(A, L.in_f64.p, L.ent_f64.p, shift, x, y, k, s);
   }
   if (vec_dtype == PARS3_F32) {
-    if (A->has_f32) return dispatch_k<float, float>(A, L.in_f32.p, L.ent_f32.p, L.far_f32.p, shift, x, y, k, s);
+    if (A->has_f32) return dispatch_k<float, float>(A, L.in_f32.p, L.ent_f32.p, shift, x, y, k, s);
     if (A->has_bf16)
-      return dispatch_k<uint16_t, float>(A, L.in_bf16.p, L.ent_bf16.p, L.far_bf16.p, shift, x, y, k, s);
+      return dispatch_k<uint16_t, float>(A, L.in_bf16.p, L.ent_bf16.p, shift, x, y, k, s);
     return fail(PARS3_ESTATE, "spmv: no FP32 or BF16 values are stored for FP32 vectors");
   }
   return fail(PARS3_EINVAL, "spmv: vec_dtype must be PARS3_F64 or PARS3_F32");

@@ -81,4 +81,4 @@ def test_validation_on_generated_inputs(L):
 
 def test_split_params_default(L):
     p = p3.pars3_split_params_default()
-    assert (p.w_in, p.t_out, p.tile_rows, p.window_max, p.permute, p.value_dtype) == (-1, -1, 256, 1024, 1, p3.F64)
+    assert (p.w_in, p.t_out, p.tile_rows, p.permute, p.value_dtype, p.keep_fp64) == (-1, -1, 256, 1, p3.F64, 0)

@@ -37,6 +37,8 @@ def check_product(L, shift=0.5, k=1, value_dtype=p3.F64, seed=11, **params):
     ("rgg_30000", lambda: synth.rgg2d(30000, 16.0, 4)),
     ("chung_lu_20000", lambda: synth.chung_lu(20000, 16.0, 2.5, 5)),
     ("pieces", lambda: synth.from_edges(40, [(i, i + 1) for i in range(0, 38, 3)], relabel=True, seed=3)),
+    ("star_hub", lambda: synth.from_edges(3000, [(0, i) for i in range(1, 3000)] + [(i, i + 1) for i in range(1, 2999)],
+                                         relabel=True, seed=4)),
 ])
 @pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32, p3.BF16])
 def test_product_parity(name, maker, value_dtype):
@@ -45,8 +47,8 @@ def test_product_parity(name, maker, value_dtype):
 
 
 @pytest.mark.parametrize("params", [
-    dict(tile_rows=64), dict(tile_rows=1024), dict(window_max=64), dict(y_mode=p3.Y_ATOMIC),
-    dict(w_in=4), dict(w_in=16, t_out=40), dict(t_out=5), dict(w_in=0, t_out=0), dict(permute=0),
+    dict(tile_rows=64), dict(tile_rows=128), dict(tile_rows=512), dict(tile_rows=1024),
+    dict(w_in=4), dict(w_in=16, t_out=40), dict(t_out=5), dict(w_in=0, t_out=0), dict(w_in=64), dict(permute=0),
 ])
 def test_layout_variants(params):
     print(f"[gpu] spmv layout {params}", flush=True)
@@ -54,7 +56,7 @@ def test_layout_variants(params):
 
 
 @pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32, p3.BF16])
-@pytest.mark.parametrize("params", [dict(), dict(w_in=3), dict(y_mode=p3.Y_ATOMIC), dict(tile_rows=64, window_max=32)])
+@pytest.mark.parametrize("params", [dict(), dict(w_in=3), dict(t_out=2), dict(tile_rows=64)])
 def test_integer_inputs_bit_exact(value_dtype, params):
     """Values and x in {-4..4}: exact in every precision and summation order."""
     L = synth.rgg2d(8000, 10.0, 12, "int4")
