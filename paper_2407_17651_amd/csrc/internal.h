@@ -15,12 +15,14 @@ namespace p3 {
 pars3_status fail(pars3_status st, const char *fmt, ...);
 void clear_error();
 
-#define P3_HIP(call)                                                                                    \
-  do {                                                                                                  \
-    hipError_t e_ = (call);                                                                             \
-    if (e_ != hipSuccess)                                                                               \
-      return ::p3::fail(e_ == hipErrorOutOfMemory ? PARS3_ENOMEM : PARS3_EHIP, "%s: %s (%s:%d)", #call, \
-                        hipGetErrorString(e_), __FILE__, __LINE__);                                     \
+#define P3_HIP(call)                                                                                      \
+  do {                                                                                                    \
+    hipError_t e_ = (call);                                                                               \
+    if (e_ != hipSuccess) {                                                                               \
+      (void)hipGetLastError(); /* do not leave the error pending for later checks */                     \
+      return ::p3::fail(e_ == hipErrorOutOfMemory ? PARS3_ENOMEM : PARS3_EHIP, "%s: %s (%s:%d)", #call,   \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                                       \
+    }                                                                                                     \
   } while (0)
 
 #define P3_TRY(expr)                     \
@@ -161,6 +163,11 @@ struct layout {
   // row tile t owns blocks [tblk_ptr[t], tblk_ptr[t+1]); column tile u is the
   // column tile of blocks ublk[ublk_ptr[u] .. ublk_ptr[u+1]) (ascending)
   dbuf<int32_t> tblk_ptr, ublk_ptr, ublk;
+  // per tile, its segments (row-side blocks, then column-side blocks):
+  // tile t reads segments [tseg_ptr[t], tseg_ptr[t+1]) with entry start
+  // seg_start, length seg_len and code (other tile << 1 | column side)
+  dbuf<int32_t> tseg_ptr, seg_start, seg_len, seg_code;
+  int32_t max_segs = 0;
   // layout position of every canonical entry (-1 for inner-band entries)
   dbuf<int32_t> pos_of;
 };

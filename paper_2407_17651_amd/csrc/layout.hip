@@ -155,6 +155,33 @@ __global__ void k_list_sort(const int32_t *__restrict__ ptr, int32_t nlists, con
   for (int32_t r = ptr[lo]; r < ptr[lo + 1]; r++) rank += in[r] < v;
   out[ptr[lo] + rank] = v;
 }
+// Segment table of every tile: its own blocks (row side) and then the blocks
+// of its column list (column side).
+__global__ void k_seg_count(const int32_t *__restrict__ tblk_ptr, const int32_t *__restrict__ ublk_ptr, int32_t ntiles,
+                            int32_t *__restrict__ cnt) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntiles) cnt[t] = (tblk_ptr[t + 1] - tblk_ptr[t]) + (ublk_ptr[t + 1] - ublk_ptr[t]);
+}
+__global__ void k_seg_fill(const int32_t *__restrict__ tblk_ptr, const int32_t *__restrict__ ublk_ptr,
+                           const int32_t *__restrict__ ublk, const int32_t *__restrict__ blk_start,
+                           const int32_t *__restrict__ blk_t, const int32_t *__restrict__ blk_u, int32_t ntiles,
+                           const int32_t *__restrict__ tseg_ptr, int32_t *__restrict__ seg_start,
+                           int32_t *__restrict__ seg_len, int32_t *__restrict__ seg_code) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  int32_t q = tseg_ptr[t];
+  for (int32_t b = tblk_ptr[t]; b < tblk_ptr[t + 1]; b++, q++) {
+    seg_start[q] = blk_start[b];
+    seg_len[q] = blk_start[b + 1] - blk_start[b];
+    seg_code[q] = blk_u[b] << 1;
+  }
+  for (int32_t r = ublk_ptr[t]; r < ublk_ptr[t + 1]; r++, q++) {
+    const int32_t b = ublk[r];
+    seg_start[q] = blk_start[b];
+    seg_len[q] = blk_start[b + 1] - blk_start[b];
+    seg_code[q] = (blk_t[b] << 1) | 1;
+  }
+}
 __global__ void k_pos_prefix(const int8_t *__restrict__ part, int64_t nnz, int32_t *__restrict__ flag) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < nnz) flag[e] = part[e] != 0;
@@ -308,6 +335,28 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
     P3_LAUNCHED();
     k_list_sort<<<nblk(nb), TB, 0, s>>>(L.ublk_ptr.p, ntiles, tmp.p, nb, L.ublk.p);
     P3_LAUNCHED();
+  }
+  // per-tile segment tables
+  {
+    dbuf<int32_t> cnt;
+    P3_HIP(cnt.alloc(ntiles));
+    P3_HIP(L.tseg_ptr.alloc(ntiles + 1));
+    if (ntiles > 0) {
+      k_seg_count<<<nblk(ntiles), TB, 0, s>>>(L.tblk_ptr.p, L.ublk_ptr.p, ntiles, cnt.p);
+      P3_LAUNCHED();
+    }
+    P3_TRY(scan_i32(cnt.p, L.tseg_ptr.p, ntiles, s));
+    int32_t nsegs = 0;
+    P3_HIP(hipMemcpyAsync(&nsegs, L.tseg_ptr.p + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P3_HIP(hipStreamSynchronize(s));
+    P3_HIP(L.seg_start.alloc(nsegs));
+    P3_HIP(L.seg_len.alloc(nsegs));
+    P3_HIP(L.seg_code.alloc(nsegs));
+    if (ntiles > 0 && nsegs > 0) {
+      k_seg_fill<<<nblk(ntiles), TB, 0, s>>>(L.tblk_ptr.p, L.ublk_ptr.p, L.ublk.p, L.blk_start.p, L.blk_t.p, L.blk_u.p,
+                                             ntiles, L.tseg_ptr.p, L.seg_start.p, L.seg_len.p, L.seg_code.p);
+      P3_LAUNCHED();
+    }
   }
   // per-tile maxima of blocks (row side and column side), for the read-back
   std::vector<int32_t> ht(ntiles + 1), hu(ntiles + 1);

@@ -28,7 +28,8 @@ namespace p3 {
 static constexpr int TB = 256;
 static constexpr int LDS_MAX = 160 * 1024;
 static constexpr int SEGS = 64;  // segments (blocks) staged per round
-static constexpr int PRE = 4;    // entries per thread whose loads are issued together
+static constexpr int PRE = 8;       // entries per thread whose loads are issued together
+static constexpr int ROWS_MAX = 4;  // own rows per thread (tiles of up to 4*TB rows)
 
 template <class V>
 struct vload;
@@ -58,37 +59,38 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
 }
 
 template <class V, class X, int K>
-__global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tblk_ptr, const int32_t *__restrict__ ublk_ptr,
-                                             const int32_t *__restrict__ ublk, const int32_t *__restrict__ blk_start,
-                                             const int32_t *__restrict__ blk_t, const int32_t *__restrict__ blk_u,
+__global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tseg_ptr, const int32_t *__restrict__ seg_start,
+                                             const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_code,
                                              const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
                                              const V *__restrict__ dia, int32_t w_in, int32_t ntiles, int32_t lgT,
                                              int32_t n, X shift, const X *__restrict__ x, X *__restrict__ y) {
-  __shared__ int32_t s_start[SEGS], s_pre[SEGS + 1], s_other[SEGS];
+  __shared__ int32_t s_start[SEGS], s_pre[SEGS + 1], s_code[SEGS];
   extern __shared__ unsigned char smem[];
   X *ys = reinterpret_cast<X *>(smem);
   const int32_t t = xcd_tile(blockIdx.x, ntiles);
   if (t >= ntiles) return;
+  const int32_t T = 1 << lgT;
   const int32_t r0 = t << lgT;
-  const int32_t rows = min(1 << lgT, n - r0);
-  const int32_t rb0 = tblk_ptr[t], nrow_seg = tblk_ptr[t + 1] - rb0;
-  const int32_t cb0 = ublk_ptr[t], ncol_seg = ublk_ptr[t + 1] - cb0;
-  const int32_t nseg = nrow_seg + ncol_seg;
+  const int32_t rows = min(T, n - r0);
+  // the own rows' x, needed at the end, requested first
+  X xown[ROWS_MAX][K];
+#pragma unroll
+  for (int q = 0; q < ROWS_MAX; q++) {
+    const int32_t r = (int32_t)threadIdx.x + q * TB;
+#pragma unroll
+    for (int c = 0; c < K; c++) xown[q][c] = r < rows ? x[((int64_t)r0 + r) * K + c] : (X)0;
+  }
+  const int32_t g0 = tseg_ptr[t], nseg = tseg_ptr[t + 1] - g0;
   for (int32_t s = threadIdx.x; s < rows * K; s += TB) ys[s] = (X)0;
   for (int32_t c0 = 0; c0 < nseg; c0 += SEGS) {
-    // stage up to SEGS segments: row-side blocks first, then column-side ones
     const int32_t cnt = min(SEGS, nseg - c0);
     if (threadIdx.x < 64) {
       const int lane = threadIdx.x;
       int32_t len = 0;
       if (lane < cnt) {
-        const int32_t g = c0 + lane;
-        const bool row_side = g < nrow_seg;
-        const int32_t b = row_side ? rb0 + g : ublk[cb0 + (g - nrow_seg)];
-        s_start[lane] = blk_start[b];
-        len = blk_start[b + 1] - blk_start[b];
-        // the other tile, negated for the column side
-        s_other[lane] = row_side ? blk_u[b] : -1 - blk_t[b];
+        s_start[lane] = seg_start[g0 + c0 + lane];
+        s_code[lane] = seg_code[g0 + c0 + lane];
+        len = seg_len[g0 + c0 + lane];
       }
       int32_t incl = len;
 #pragma unroll
@@ -118,21 +120,17 @@ __global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tblk_pt
             else hi = mid - 1;
           }
           const int64_t e = (int64_t)s_start[lo] + (v - s_pre[lo]);
-          const int32_t other = s_other[lo];
-          // row side: last use of the block (nontemporal); column side: first
-          // use, keep it in L2 for the row tile that reads it later
-          const uint32_t rc = other >= 0 ? __builtin_nontemporal_load(ent_rc + e) : ent_rc[e];
-          const X val = other >= 0 ? (X)vload<V>::nt(ent_v, e) : (X)vload<V>::ld(ent_v, e);
+          const int32_t code = s_code[lo];
+          const int32_t other = code >> 1;
+          // the column side reads a block first and leaves it in L2; the row
+          // side is its last use (nontemporal)
+          const bool col_side = code & 1;
+          const uint32_t rc = col_side ? ent_rc[e] : __builtin_nontemporal_load(ent_rc + e);
+          const X val = col_side ? (X)vload<V>::ld(ent_v, e) : (X)vload<V>::nt(ent_v, e);
           const int32_t ri = (int32_t)(rc >> 16), cj = (int32_t)(rc & 0xffffu);
-          if (other >= 0) {
-            slot[q] = ri;
-            xrow[q] = (other << lgT) + cj;
-            coef[q] = val;
-          } else {
-            slot[q] = cj;
-            xrow[q] = ((-1 - other) << lgT) + ri;
-            coef[q] = -val;
-          }
+          slot[q] = col_side ? cj : ri;
+          xrow[q] = (other << lgT) + (col_side ? ri : cj);
+          coef[q] = col_side ? -val : val;
         }
       }
 #pragma unroll
@@ -149,11 +147,14 @@ __global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tblk_pt
     __syncthreads();  // the segment table is rewritten by the next round
   }
   if (nseg == 0) __syncthreads();
-  for (int32_t r = threadIdx.x; r < rows; r += TB) {
+#pragma unroll
+  for (int q = 0; q < ROWS_MAX; q++) {
+    const int32_t r = (int32_t)threadIdx.x + q * TB;
+    if (r >= rows) continue;
     const int64_t i = r0 + r;
     X acc[K];
 #pragma unroll
-    for (int c = 0; c < K; c++) acc[c] = shift * x[i * K + c] + ys[r * K + c];
+    for (int c = 0; c < K; c++) acc[c] = shift * xown[q][c] + ys[r * K + c];
     for (int32_t k = 1; k <= w_in; k++) {
       const int64_t bse = (int64_t)(k - 1) * n;
       if (i - k >= 0) {
@@ -181,11 +182,12 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   const layout &L = A->lay;
   const int32_t n = (int32_t)A->n;
   if (n == 0) return PARS3_OK;
+  if (L.T > ROWS_MAX * TB) return fail(PARS3_EINVAL, "spmv: tile_rows above %d", ROWS_MAX * TB);
   const size_t lds = (size_t)L.T * K * sizeof(X);
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
-  k_pair<V, X, K><<<grid, TB, lds, s>>>(L.tblk_ptr.p, L.ublk_ptr.p, L.ublk.p, L.blk_start.p, L.blk_t.p, L.blk_u.p,
-                                        L.ent_rc.p, ent_v, in_v, L.w_in, L.ntiles, L.lgT, n, shift, x, y);
+  k_pair<V, X, K><<<grid, TB, lds, s>>>(L.tseg_ptr.p, L.seg_start.p, L.seg_len.p, L.seg_code.p, L.ent_rc.p, ent_v, in_v,
+                                        L.w_in, L.ntiles, L.lgT, n, shift, x, y);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;
