@@ -28,8 +28,7 @@ namespace p3 {
 static constexpr int TB = 256;
 static constexpr int LDS_MAX = 160 * 1024;
 static constexpr int SEGS = 64;  // segments (blocks) staged per round
-static constexpr int PRE = 8;       // entries per thread whose loads are issued together
-static constexpr int ROWS_MAX = 4;  // own rows per thread (tiles of up to 4*TB rows)
+static constexpr int PRE = 4;  // entries per thread whose loads are issued together
 
 template <class V>
 struct vload;
@@ -72,14 +71,10 @@ __global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tseg_pt
   const int32_t T = 1 << lgT;
   const int32_t r0 = t << lgT;
   const int32_t rows = min(T, n - r0);
-  // the own rows' x, needed at the end, requested first
-  X xown[ROWS_MAX][K];
+  // x of the thread's first own row, needed at the end, requested first
+  X xown[K];
 #pragma unroll
-  for (int q = 0; q < ROWS_MAX; q++) {
-    const int32_t r = (int32_t)threadIdx.x + q * TB;
-#pragma unroll
-    for (int c = 0; c < K; c++) xown[q][c] = r < rows ? x[((int64_t)r0 + r) * K + c] : (X)0;
-  }
+  for (int c = 0; c < K; c++) xown[c] = (int32_t)threadIdx.x < rows ? x[((int64_t)r0 + threadIdx.x) * K + c] : (X)0;
   const int32_t g0 = tseg_ptr[t], nseg = tseg_ptr[t + 1] - g0;
   for (int32_t s = threadIdx.x; s < rows * K; s += TB) ys[s] = (X)0;
   for (int32_t c0 = 0; c0 < nseg; c0 += SEGS) {
@@ -147,14 +142,11 @@ __global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tseg_pt
     __syncthreads();  // the segment table is rewritten by the next round
   }
   if (nseg == 0) __syncthreads();
-#pragma unroll
-  for (int q = 0; q < ROWS_MAX; q++) {
-    const int32_t r = (int32_t)threadIdx.x + q * TB;
-    if (r >= rows) continue;
+  for (int32_t r = threadIdx.x; r < rows; r += TB) {
     const int64_t i = r0 + r;
     X acc[K];
 #pragma unroll
-    for (int c = 0; c < K; c++) acc[c] = shift * xown[q][c] + ys[r * K + c];
+    for (int c = 0; c < K; c++) acc[c] = shift * (r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c]) + ys[r * K + c];
     for (int32_t k = 1; k <= w_in; k++) {
       const int64_t bse = (int64_t)(k - 1) * n;
       if (i - k >= 0) {
@@ -182,7 +174,6 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   const layout &L = A->lay;
   const int32_t n = (int32_t)A->n;
   if (n == 0) return PARS3_OK;
-  if (L.T > ROWS_MAX * TB) return fail(PARS3_EINVAL, "spmv: tile_rows above %d", ROWS_MAX * TB);
   const size_t lds = (size_t)L.T * K * sizeof(X);
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
