@@ -173,6 +173,60 @@ pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x, void *y, 
 pars3_status pars3_csr_get(const pars3_csr *C, int32_t *rowptr, int32_t *col, double *val);
 void pars3_csr_destroy(pars3_csr *C);
 
+/* MRS solver for (alpha*I + S) x = b (Section 1: the minimal-residual method
+ * for shifted skew-symmetric systems that motivates the product; each
+ * iteration costs one product with S and one inner product).  x_k minimises
+ * ||b - A x|| over x_0 + K_k(S, r_0) by a skew Lanczos recurrence with Givens
+ * rotations.  Every iteration runs on the device (product with a fused
+ * epilogue, one scalar kernel, one vector kernel, replayed from a hipGraph);
+ * the host polls the stop flag every check_every iterations.
+ *
+ * precision = PARS3_F64: the whole iteration in FP64 (needs FP64 values).
+ * precision = PARS3_F32 / PARS3_BF16: mixed precision; FP64 iterative
+ * refinement (residual b - A x with FP64 values and vectors) around inner MRS
+ * solves whose matrix values are FP32 / BF16 and vectors FP32, with FP64 inner
+ * products and scalars; each inner solve reduces its residual by inner_tol
+ * (0 = 1e-6 for FP32, 1e-2 for BF16); at most max_refine refinements.  Needs a
+ * layout built with value_dtype F32 / BF16 and keep_fp64 = 1.
+ *
+ * Stopping: ||b - A x|| <= tol ||b|| (for FP64, the recurrence's |eta|;
+ * maxit bounds the total number of iterations (inner ones for mixed).  b and x
+ * (initial guess in, solution out) are device FP64 arrays of n values in the
+ * numbering selected by order.  hist (host, hist_len values, may be NULL when
+ * hist_len = 0) receives |eta_j|/||b|| of the first iterations.  The stream is
+ * the caller's: the solve starts after work already queued on it and is
+ * synchronous (returns when x is written).  info (may be NULL) receives
+ * iteration counts, the final status and the true relative residual
+ * ||b - A x||/||b|| of the returned x computed in FP64.
+ * Errors: ESTATE before pars3_reorder or when the needed values are not
+ * stored; EINVAL for bad options; ENOCONV when the tolerance was not reached
+ * (x holds the last iterate); EBREAKDOWN when gamma = 0 (singular A, e.g.
+ * alpha = 0 with n odd); ENAN when a NaN or Inf appears. */
+typedef struct {
+  double tol;           /* relative residual target (default 1e-10) */
+  int32_t maxit;        /* iteration limit (default 10000) */
+  int32_t check_every;  /* iterations between host polls of the stop flag (default 32) */
+  int32_t precision;    /* PARS3_F64 (default), PARS3_F32 or PARS3_BF16 */
+  double inner_tol;     /* mixed: relative reduction of each inner solve (0 = default) */
+  int32_t max_refine;   /* mixed: maximum number of refinements (default 30) */
+  int32_t order;        /* PARS3_ORDER_RCM (default) or PARS3_ORDER_ORIGINAL */
+  int32_t hist_len;     /* length of hist (0 = no history) */
+  double *hist;         /* host array of hist_len values, or NULL */
+} pars3_mrs_opts;
+
+typedef struct {
+  int32_t iters;       /* total MRS iterations (inner ones for mixed) */
+  int32_t refinements; /* mixed: outer refinement steps taken */
+  int32_t status;      /* 0 converged, 1 iteration limit, 2 breakdown, 3 NaN/Inf */
+  double relres;       /* ||b - A x|| / ||b|| of the returned x (FP64) */
+  double eta;          /* FP64: |eta|/||b|| of the recurrence; mixed: relres */
+  double time_ms;      /* wall time of the call */
+} pars3_mrs_info;
+
+void pars3_mrs_opts_default(pars3_mrs_opts *o);
+pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, double *x, const pars3_mrs_opts *opts,
+                             pars3_mrs_info *info, void *stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *pars3_last_error(void);
 

@@ -62,6 +62,20 @@ class Profile(ctypes.Structure):
                 ("ms_other", ctypes.c_double)]
 
 
+class MrsOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("hist_len", ctypes.c_int32), ("hist", ctypes.c_void_p)]
+
+
+class MrsInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("refinements", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("eta", ctypes.c_double), ("time_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i32, _i64, _d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _st = ctypes.c_int
@@ -84,6 +98,8 @@ SIGNATURES = {
     "pars3_csr_spmv": ([_vp, _d, _vp, _vp, _i32, _vp], _st),
     "pars3_csr_get": ([_vp, _vp, _vp, _vp], _st),
     "pars3_csr_destroy": ([_vp], None),
+    "pars3_mrs_opts_default": ([ctypes.POINTER(MrsOpts)], None),
+    "pars3_mrs_solve": ([_vp, _d, _vp, _vp, ctypes.POINTER(MrsOpts), ctypes.POINTER(MrsInfo), _vp], _st),
     "pars3_last_error": ([], ctypes.c_char_p),
 }
 
@@ -244,6 +260,23 @@ def pars3_csr_destroy(c):
         lib().pars3_csr_destroy(c)
 
 
+def pars3_mrs_opts_default() -> MrsOpts:
+    o = MrsOpts()
+    lib().pars3_mrs_opts_default(ctypes.byref(o))
+    return o
+
+
+def pars3_mrs_solve(h, alpha, b, x, opts: MrsOpts | None = None, stream=None, check=True):
+    """Solves (alpha*I + S) x = b in place of x (device FP64 tensors).  Returns
+    (status, info dict); raises Pars3Error on a non-OK status when check."""
+    info = MrsInfo()
+    st = int(lib().pars3_mrs_solve(h, float(alpha), _ptr(b), _ptr(x), ctypes.byref(opts) if opts is not None else None,
+                                   ctypes.byref(info), _stream(stream)))
+    if check:
+        _check(st, "pars3_mrs_solve")
+    return st, info.as_dict()
+
+
 # ------------------------------------------------------------------ convenience wrapper
 class Matrix:
     """Owning wrapper of a ``pars3_matrix`` handle built from a strictly lower
@@ -278,6 +311,18 @@ class Matrix:
         vd = F64 if x.dtype == torch.float64 else F32
         pars3_spmv(self.h, shift, x, y, k, vd, order, stream)
         return y
+
+    def mrs(self, alpha, b, x, hist_len=0, check=True, stream=None, **kw):
+        """MRS solve; keyword options as in pars3_mrs_opts.  Returns
+        (status, info, hist) with hist a numpy array of hist_len values."""
+        o = pars3_mrs_opts_default()
+        for k, v in kw.items():
+            setattr(o, k, type(getattr(o, k))(v))
+        hist = np.zeros(max(hist_len, 1), np.float64)
+        o.hist_len = int(hist_len)
+        o.hist = hist.ctypes.data if hist_len else None
+        st, info = pars3_mrs_solve(self.h, alpha, b, x, o, stream, check)
+        return st, info, hist[:min(hist_len, info["iters"])].copy()
 
     def perm(self):
         return pars3_get_perm(self.h, self.n)

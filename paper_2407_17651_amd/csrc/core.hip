@@ -67,6 +67,8 @@ extern "C" pars3_status pars3_create(int64_t n, int64_t nnz, const int32_t *rowp
 }
 
 pars3_matrix::~pars3_matrix() {
+  p3::mrs_ws_free(mrs);
+  if (solver_stream) (void)hipStreamDestroy(solver_stream);
   for (auto &v : prof.ev)
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
 }

@@ -172,6 +172,9 @@ struct layout {
   dbuf<int32_t> pos_of;
 };
 
+struct mrs_ws;
+void mrs_ws_free(mrs_ws *w);
+
 }  // namespace p3
 
 struct pars3_matrix {
@@ -197,6 +200,9 @@ struct pars3_matrix {
   bool has_f64 = false, has_f32 = false, has_bf16 = false;
   // scratch for products in the caller's numbering
   p3::dbuf<char> xr, yr;
+  // solver stream and workspace (mrs.hip), created on first use
+  hipStream_t solver_stream = nullptr;
+  p3::mrs_ws *mrs = nullptr;
   // per-kernel event timing (pars3_set_profiling)
   struct {
     bool on = false;
@@ -216,6 +222,21 @@ pars3_status permute_gpu(pars3_matrix *A, hipStream_t s);
 pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipStream_t s);
 // spmv.hip
 enum { PROF_BAND = 0, PROF_FIXUP = 1, PROF_OTHER = 2 };
+// Optional epilogue of the product kernel (used by the solvers):
+//   y += (*beta) * z                      when z != nullptr,
+//   partials[t] = sum over tile t of y^2  when partials != nullptr (FP64),
+//   the whole launch is skipped           when done != nullptr and *done != 0.
+template <class X>
+struct epilogue {
+  const X *z = nullptr;
+  const double *beta = nullptr;
+  double *partials = nullptr;
+  const int32_t *done = nullptr;
+};
+// Product with an optional epilogue; value_dtype selects FP32 or BF16 values
+// when both are stored (-1: whichever is stored).
+pars3_status spmv_ex(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, int value_dtype,
+                     hipStream_t s, const void *ep);
 pars3_status prof_mark(pars3_matrix *A, int cls, int stop, hipStream_t s);
 pars3_status spmv_rcm(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, hipStream_t s);
 pars3_status gather_rows(const void *src, void *dst, const int32_t *idx, int64_t n, int k, size_t elem,

@@ -1,0 +1,468 @@
+// MRS for shifted skew-symmetric systems (alpha*I + S) x = b (Section 1:
+// the minimal-residual method for (shifted) skew-symmetric systems needs one
+// product with S and one inner product per iteration).
+//
+// Recurrence.  Skew Lanczos: w = S v_j + beta_j v_{j-1}, beta_{j+1} = ||w||,
+// v_{j+1} = w / beta_{j+1}, so (alpha*I + S) V_k = V_{k+1} H_k where column j
+// of H_k holds -beta_j (row j-1), alpha (row j) and beta_{j+1} (row j+1).  H_k
+// is reduced by Givens rotations as in MINRES; |eta| is the residual norm.
+//
+// One iteration is three launches on one stream, captured once in a hipGraph
+// (two iterations, because buffer roles alternate) and replayed:
+//   1. the product kernel with the solver epilogue: w = S v_j + beta_j v_{j-1}
+//      and per-tile partial sums of w^2 in FP64 (the inner product);
+//   2. k_mrs_scalar, one workgroup: sums the partials in a fixed order,
+//      updates the rotations and eta, records |eta|/||b||, decides to stop;
+//   3. k_mrs_vec: p_j = (v_j - delta p_{j-1} - eps p_{j-2}) / gamma,
+//      x += c eta p_j, v_{j+1} = w / beta_{j+1}.
+// Scalars live on the device; the host reads the stop flag every
+// check_every iterations.  Once stopped, every later kernel returns at once.
+//
+// Mixed precision: iterative refinement in FP64 around an inner MRS whose
+// matrix values and vectors are FP32 (or BF16 values with FP32 vectors) while
+// its inner products and scalars stay FP64:
+//   r = b - A x (FP64 values and vectors); stop when ||r|| <= tol ||b||;
+//   solve (alpha*I + S~) d = r to relative tolerance inner_tol; x += d.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace p3 {
+
+static constexpr int TB = 256;
+static inline unsigned nblk(int64_t m) { return (unsigned)std::max<int64_t>(1, cdiv(m, TB)); }
+
+// Device state of one MRS run.  Rotation state is double-buffered by
+// iteration parity: iteration j reads slot j&1 and writes slot (j+1)&1.
+struct mrs_dev {
+  double beta[2], c1[2], s1[2], c2[2], s2[2], eta[2];
+  double delta, eps, gamma, ceta, inv_beta;  // this iteration, for k_mrs_vec
+  double bnorm, tol_abs, alpha, minus_one;
+  int32_t iter, maxit, done, active, status;  // status: 0 ok, 1 maxit, 2 breakdown, 3 nan
+};
+
+__global__ __launch_bounds__(TB) void k_mrs_scalar(mrs_dev *d, int par, const double *__restrict__ partials, int32_t np,
+                                                  double *__restrict__ hist) {
+  __shared__ double red[TB];
+  if (d->done) {
+    if (threadIdx.x == 0) d->active = 0;
+    return;
+  }
+  double sum = 0.0;
+  for (int32_t q = threadIdx.x; q < np; q += TB) sum += partials[q];
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = TB / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double beta_n = sqrt(red[0]);
+  const double beta_j = d->beta[par], c1 = d->c1[par], s1 = d->s1[par], c2 = d->c2[par], s2 = d->s2[par];
+  const double eta = d->eta[par], alpha = d->alpha;
+  const double eps = s2 * (-beta_j);
+  const double dbar = c2 * (-beta_j);
+  const double delta = c1 * dbar + s1 * alpha;
+  const double gbar = -s1 * dbar + c1 * alpha;
+  const double gamma = sqrt(gbar * gbar + beta_n * beta_n);
+  if (!isfinite(beta_n) || !isfinite(gamma)) {
+    d->status = 3;
+    d->done = 1;
+    d->active = 0;
+    return;
+  }
+  if (gamma == 0.0) {
+    d->status = 2;
+    d->done = 1;
+    d->active = 0;
+    return;
+  }
+  const double c = gbar / gamma, s = beta_n / gamma;
+  d->delta = delta;
+  d->eps = eps;
+  d->gamma = gamma;
+  d->ceta = c * eta;
+  d->inv_beta = beta_n > 0.0 ? 1.0 / beta_n : 0.0;
+  d->active = 1;
+  const double eta_n = -s * eta;
+  const int32_t it = d->iter + 1;
+  d->iter = it;
+  if (hist) hist[it - 1] = fabs(eta_n) / d->bnorm;
+  const int q = par ^ 1;
+  d->beta[q] = beta_n;
+  d->c1[q] = c;
+  d->s1[q] = s;
+  d->c2[q] = c1;
+  d->s2[q] = s1;
+  d->eta[q] = eta_n;
+  if (fabs(eta_n) <= d->tol_abs || beta_n == 0.0) {
+    d->done = 1;
+  } else if (it >= d->maxit) {
+    d->done = 1;
+    d->status = 1;
+  }
+}
+
+template <class X>
+__global__ __launch_bounds__(TB) void k_mrs_vec(const mrs_dev *__restrict__ d, int64_t n, const X *__restrict__ v,
+                                               const X *__restrict__ w, const X *__restrict__ p1, X *p2, X *x,
+                                               X *vnext) {
+  if (!d->active) return;
+  const double delta = d->delta, eps = d->eps, gamma = d->gamma, ceta = d->ceta, ib = d->inv_beta;
+  for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+    const double pn = ((double)v[i] - delta * (double)p1[i] - eps * (double)p2[i]) / gamma;
+    p2[i] = (X)pn;
+    x[i] = (X)((double)x[i] + ceta * pn);
+    vnext[i] = (X)((double)w[i] * ib);
+  }
+}
+
+// v = -y * inv (the start vector from y = A x - b), in the inner precision
+template <class XI, class XO>
+__global__ void k_neg_scale(const XI *__restrict__ y, XO *__restrict__ v, double inv, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) v[i] = (XO)(-(double)y[i] * inv);
+}
+template <class X>
+__global__ void k_zero(X *__restrict__ a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) a[i] = (X)0;
+}
+template <class X>
+__global__ void k_add_to_f64(double *__restrict__ x, const X *__restrict__ d, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) x[i] += (double)d[i];
+}
+__global__ void k_sumsq_partials(const double *__restrict__ a, int64_t n, double *__restrict__ partials) {
+  __shared__ double red[TB];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) s += a[i] * a[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = TB / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------ host side
+struct mrs_ws {
+  dbuf<char> vb0, vb1, w, pb0, pb1, xin;  // inner-precision vectors
+  dbuf<double> xr, br, yr;                 // FP64 solution, rhs, residual (reordered numbering)
+  dbuf<double> partials, hist;
+  dbuf<mrs_dev> dev;
+};
+
+static pars3_status sum_partials(const double *partials, int64_t np, hipStream_t s, double *out) {
+  std::vector<double> h(std::max<int64_t>(np, 1));
+  if (np) P3_HIP(hipMemcpyAsync(h.data(), partials, np * sizeof(double), hipMemcpyDeviceToHost, s));
+  P3_HIP(hipStreamSynchronize(s));
+  double t = 0.0;
+  for (int64_t q = 0; q < np; q++) t += h[q];
+  *out = t;
+  return PARS3_OK;
+}
+
+// y = alpha x + S x - b (FP64); returns ||y||
+static pars3_status residual64(pars3_matrix *A, double alpha, const double *x, const double *b, double *y,
+                               double *partials, const double *minus_one, hipStream_t s, double *rnorm) {
+  epilogue<double> ep;
+  ep.z = b;
+  ep.beta = minus_one;
+  ep.partials = partials;
+  P3_TRY(spmv_ex(A, alpha, x, y, 1, PARS3_F64, -1, s, &ep));
+  double ss = 0.0;
+  P3_TRY(sum_partials(partials, A->lay.ntiles, s, &ss));
+  *rnorm = std::sqrt(ss);
+  return PARS3_OK;
+}
+
+// Runs MRS iterations from the normalized start vector already in vb0 (v_1),
+// accumulating into x (inner precision), until |eta| <= tol_abs, maxit, or a
+// breakdown.  Iteration counts, status and the last |eta| are returned.
+template <class X>
+static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, double beta1, double bnorm,
+                                double tol_abs, int32_t maxit, int32_t check_every, mrs_ws &ws, X *x, hipStream_t s,
+                                int32_t *iters, int32_t *status, double *eta_out, double *hist) {
+  const int64_t n = A->n;
+  const int vec = sizeof(X) == 8 ? PARS3_F64 : PARS3_F32;
+  X *V[2] = {(X *)ws.vb0.p, (X *)ws.vb1.p};
+  X *P[2] = {(X *)ws.pb0.p, (X *)ws.pb1.p};
+  X *W = (X *)ws.w.p;
+  // state: v_0 = 0, p_0 = p_{-1} = 0, rotations identity, eta = beta_1
+  k_zero<X><<<nblk(n), TB, 0, s>>>(V[1], n);
+  k_zero<X><<<nblk(n), TB, 0, s>>>(P[0], n);
+  k_zero<X><<<nblk(n), TB, 0, s>>>(P[1], n);
+  P3_LAUNCHED();
+  mrs_dev h{};
+  h.beta[0] = 0.0;
+  h.c1[0] = 1.0;
+  h.s1[0] = 0.0;
+  h.c2[0] = 1.0;
+  h.s2[0] = 0.0;
+  h.eta[0] = beta1;
+  h.bnorm = bnorm > 0.0 ? bnorm : 1.0;
+  h.tol_abs = tol_abs;
+  h.alpha = alpha;
+  h.minus_one = -1.0;
+  h.iter = 0;
+  h.maxit = maxit;
+  h.done = (beta1 == 0.0 || beta1 <= tol_abs || maxit <= 0) ? 1 : 0;
+  h.active = 0;
+  h.status = 0;
+  P3_HIP(hipMemcpyAsync(ws.dev.p, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  const int32_t np = A->lay.ntiles;
+  // capture two iterations
+  const bool prof = A->prof.on;
+  A->prof.on = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  pars3_status st = PARS3_OK;
+  hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (ce == hipSuccess) {
+    for (int par = 0; par < 2 && st == PARS3_OK; par++) {
+      epilogue<X> ep;
+      ep.z = V[par ^ 1];
+      ep.beta = &ws.dev.p->beta[par];
+      ep.partials = ws.partials.p;
+      ep.done = &ws.dev.p->done;
+      st = spmv_ex(A, 0.0, V[par], W, 1, vec, value_dtype, s, &ep);
+      if (st != PARS3_OK) break;
+      k_mrs_scalar<<<1, TB, 0, s>>>(ws.dev.p, par, ws.partials.p, np, hist);
+      k_mrs_vec<X><<<std::min<unsigned>(nblk(n), 4096u), TB, 0, s>>>(ws.dev.p, n, V[par], W, P[par], P[par ^ 1], x,
+                                                                        V[par ^ 1]);
+    }
+    hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (st == PARS3_OK && ee != hipSuccess) st = fail(PARS3_EHIP, "mrs: stream capture failed: %s", hipGetErrorString(ee));
+  } else {
+    st = fail(PARS3_EHIP, "mrs: cannot capture the solver stream: %s", hipGetErrorString(ce));
+  }
+  A->prof.on = prof;
+  if (st == PARS3_OK) {
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) st = fail(PARS3_EHIP, "mrs: graph instantiation failed: %s", hipGetErrorString(ie));
+  }
+  int32_t done = h.done;
+  const int32_t chunk = std::max(1, check_every / 2);
+  for (int32_t it = 0; st == PARS3_OK && !done && it < maxit; it += 2 * chunk) {
+    for (int32_t c = 0; c < chunk; c++) {
+      hipError_t le = hipGraphLaunch(exec, s);
+      if (le != hipSuccess) {
+        st = fail(PARS3_EHIP, "mrs: graph launch failed: %s", hipGetErrorString(le));
+        break;
+      }
+    }
+    if (st != PARS3_OK) break;
+    hipError_t me = hipMemcpyAsync(&h, ws.dev.p, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (me == hipSuccess) me = hipStreamSynchronize(s);
+    if (me != hipSuccess) st = fail(PARS3_EHIP, "mrs: %s", hipGetErrorString(me));
+    done = h.done;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (st != PARS3_OK) {
+    (void)hipGetLastError();
+    return st;
+  }
+  P3_HIP(hipMemcpyAsync(&h, ws.dev.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  P3_HIP(hipStreamSynchronize(s));
+  *iters = h.iter;
+  *status = h.status;
+  *eta_out = std::fabs(h.eta[h.iter & 1]);
+  return PARS3_OK;
+}
+
+template <class T>
+static hipError_t fit(dbuf<T> &b, size_t m) {
+  return b.p && b.n == m ? hipSuccess : b.alloc(m);
+}
+
+// Workspace kept in the handle between solves; resized when n, the inner
+// precision or the history length change.
+static pars3_status ensure_ws(mrs_ws &ws, int64_t n, int32_t ntiles, size_t inner_elem, int32_t hist_len) {
+  const size_t vb = (size_t)std::max<int64_t>(n, 1) * inner_elem;
+  const size_t n1 = (size_t)std::max<int64_t>(n, 1);
+  P3_HIP(fit(ws.vb0, vb));
+  P3_HIP(fit(ws.vb1, vb));
+  P3_HIP(fit(ws.w, vb));
+  P3_HIP(fit(ws.pb0, vb));
+  P3_HIP(fit(ws.pb1, vb));
+  P3_HIP(fit(ws.xin, vb));
+  P3_HIP(fit(ws.xr, n1));
+  P3_HIP(fit(ws.br, n1));
+  P3_HIP(fit(ws.yr, n1));
+  P3_HIP(fit(ws.partials, (size_t)std::max<int64_t>(std::max(ntiles, 1), 1024)));
+  if (hist_len > 0) P3_HIP(fit(ws.hist, (size_t)hist_len));
+  P3_HIP(fit(ws.dev, 1));
+  return PARS3_OK;
+}
+
+void mrs_ws_free(mrs_ws *w) { delete w; }
+
+}  // namespace p3
+
+using p3::fail;
+
+extern "C" void pars3_mrs_opts_default(pars3_mrs_opts *o) {
+  if (!o) return;
+  o->tol = 1e-10;
+  o->maxit = 10000;
+  o->check_every = 32;
+  o->precision = PARS3_F64;
+  o->inner_tol = 0.0;
+  o->max_refine = 30;
+  o->order = PARS3_ORDER_RCM;
+  o->hist_len = 0;
+  o->hist = nullptr;
+}
+
+extern "C" pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, double *x,
+                                        const pars3_mrs_opts *opts, pars3_mrs_info *info, void *stream) {
+  using namespace p3;
+  if (!A) return fail(PARS3_EINVAL, "mrs: NULL handle");
+  if (!A->split_done) return fail(PARS3_ESTATE, "mrs: call pars3_reorder first");
+  pars3_mrs_opts o;
+  if (opts) o = *opts;
+  else pars3_mrs_opts_default(&o);
+  if (!(o.tol >= 0.0) || o.maxit < 0 || o.check_every < 1 || o.max_refine < 1 || o.hist_len < 0 ||
+      (o.hist_len > 0 && !o.hist))
+    return fail(PARS3_EINVAL, "mrs: bad options");
+  if (o.order != PARS3_ORDER_RCM && o.order != PARS3_ORDER_ORIGINAL) return fail(PARS3_EINVAL, "mrs: bad order");
+  if (o.precision != PARS3_F64 && o.precision != PARS3_F32 && o.precision != PARS3_BF16)
+    return fail(PARS3_EINVAL, "mrs: bad precision");
+  if (!A->has_f64) return fail(PARS3_ESTATE, "mrs: FP64 values are needed (value_dtype F64 or keep_fp64)");
+  if (o.precision == PARS3_F32 && !A->has_f32)
+    return fail(PARS3_ESTATE, "mrs: FP32 inner solves need value_dtype = PARS3_F32 with keep_fp64");
+  if (o.precision == PARS3_BF16 && !A->has_bf16)
+    return fail(PARS3_ESTATE, "mrs: BF16 inner solves need value_dtype = PARS3_BF16 with keep_fp64");
+  const int64_t n = A->n;
+  if (n > 0 && (!b || !x)) return fail(PARS3_EINVAL, "mrs: NULL vector");
+  pars3_mrs_info inf{};
+  if (n == 0) {
+    if (info) *info = inf;
+    return PARS3_OK;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t caller = (hipStream_t)stream;
+  if (!A->solver_stream) {
+    P3_HIP(hipStreamCreateWithFlags(&A->solver_stream, hipStreamNonBlocking));
+  }
+  hipStream_t s = A->solver_stream;
+  {
+    hipEvent_t ev;
+    P3_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    P3_HIP(hipEventRecord(ev, caller));
+    P3_HIP(hipStreamWaitEvent(s, ev, 0));
+    P3_HIP(hipEventDestroy(ev));
+  }
+  const bool mixed = o.precision != PARS3_F64;
+  if (!A->mrs) A->mrs = new (std::nothrow) mrs_ws;
+  if (!A->mrs) return fail(PARS3_ENOMEM, "mrs: out of host memory");
+  mrs_ws &ws = *A->mrs;
+  const int32_t hist_len = o.hist_len > 0 ? std::max(o.hist_len, o.maxit) : 0;
+  P3_TRY(ensure_ws(ws, n, A->lay.ntiles, mixed ? sizeof(float) : sizeof(double), hist_len));
+  // b and x0 in the reordered numbering
+  if (o.order == PARS3_ORDER_ORIGINAL) {
+    P3_TRY(gather_rows(b, ws.br.p, A->perm.p, n, 1, 8, s));
+    P3_TRY(gather_rows(x, ws.xr.p, A->perm.p, n, 1, 8, s));
+  } else {
+    P3_HIP(hipMemcpyAsync(ws.br.p, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    P3_HIP(hipMemcpyAsync(ws.xr.p, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  // ||b||
+  const unsigned nbk = std::min<unsigned>(nblk(n), 1024u);
+  k_sumsq_partials<<<nbk, TB, 0, s>>>(ws.br.p, n, ws.partials.p);
+  P3_LAUNCHED();
+  double bb = 0.0;
+  P3_TRY(sum_partials(ws.partials.p, nbk, s, &bb));
+  const double bnorm = std::sqrt(bb);
+  const double bscale = bnorm > 0.0 ? bnorm : 1.0;
+  // constant -1 for the residual epilogue
+  mrs_dev hd{};
+  hd.minus_one = -1.0;
+  P3_HIP(hipMemcpyAsync(ws.dev.p, &hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  P3_HIP(hipStreamSynchronize(s));
+  const double *minus_one = &ws.dev.p->minus_one;
+  double rnorm = 0.0;
+  int32_t iters = 0, status = 0, refine = 0;
+  double eta = 0.0;
+  pars3_status st = PARS3_OK;
+  if (!mixed) {
+    // r0 = b - A x0: y = A x0 - b, v_1 = -y / ||y||
+    P3_TRY(residual64(A, alpha, ws.xr.p, ws.br.p, ws.yr.p, ws.partials.p, minus_one, s, &rnorm));
+    if (rnorm > 0.0) {
+      k_neg_scale<double, double><<<nblk(n), TB, 0, s>>>(ws.yr.p, (double *)ws.vb0.p, 1.0 / rnorm, n);
+      P3_LAUNCHED();
+    }
+    st = mrs_iterate<double>(A, -1, alpha, rnorm, bscale, o.tol * bnorm, o.maxit, o.check_every, ws, ws.xr.p, s,
+                             &iters, &status, &eta, hist_len > 0 ? ws.hist.p : nullptr);
+    if (st != PARS3_OK) return st;
+  } else {
+    const double itol = o.inner_tol > 0.0 ? o.inner_tol : (o.precision == PARS3_F32 ? 1e-6 : 1e-2);
+    int32_t budget = o.maxit;
+    status = 1;
+    for (refine = 0; refine <= o.max_refine; refine++) {
+      P3_TRY(residual64(A, alpha, ws.xr.p, ws.br.p, ws.yr.p, ws.partials.p, minus_one, s, &rnorm));
+      if (!std::isfinite(rnorm)) {
+        status = 3;
+        break;
+      }
+      if (rnorm <= o.tol * bnorm) {
+        status = 0;
+        break;
+      }
+      if (budget <= 0 || refine == o.max_refine) {
+        status = 1;
+        break;
+      }
+      // inner solve (alpha*I + S~) d = r, r = -y, from d = 0
+      k_neg_scale<double, float><<<nblk(n), TB, 0, s>>>(ws.yr.p, (float *)ws.vb0.p, 1.0 / rnorm, n);
+      k_zero<float><<<nblk(n), TB, 0, s>>>((float *)ws.xin.p, n);
+      P3_LAUNCHED();
+      int32_t it = 0, ist = 0;
+      double ieta = 0.0;
+      st = mrs_iterate<float>(A, o.precision, alpha, rnorm, bscale, itol * rnorm, budget, o.check_every, ws,
+                              (float *)ws.xin.p, s, &it, &ist, &ieta, hist_len > 0 ? ws.hist.p + iters : nullptr);
+      if (st != PARS3_OK) return st;
+      iters += it;
+      budget -= it;
+      k_add_to_f64<float><<<nblk(n), TB, 0, s>>>(ws.xr.p, (const float *)ws.xin.p, n);
+      P3_LAUNCHED();
+      if (ist == 2 || ist == 3) {
+        status = ist;
+        break;
+      }
+      if (it == 0) {  // no progress possible
+        status = 1;
+        break;
+      }
+    }
+  }
+  // true FP64 residual of the returned x
+  P3_TRY(residual64(A, alpha, ws.xr.p, ws.br.p, ws.yr.p, ws.partials.p, minus_one, s, &rnorm));
+  if (o.order == PARS3_ORDER_ORIGINAL) P3_TRY(scatter_rows(ws.xr.p, x, A->perm.p, n, 1, 8, s));
+  else P3_HIP(hipMemcpyAsync(x, ws.xr.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (hist_len > 0 && iters > 0)
+    P3_HIP(hipMemcpyAsync(o.hist, ws.hist.p, std::min(iters, o.hist_len) * sizeof(double), hipMemcpyDeviceToHost, s));
+  P3_HIP(hipStreamSynchronize(s));
+  inf.iters = iters;
+  inf.refinements = mixed ? refine : 0;
+  inf.relres = rnorm / bscale;
+  inf.eta = mixed ? inf.relres : eta / bscale;
+  if (!std::isfinite(rnorm)) status = 3;
+  else if (inf.relres <= o.tol) status = 0;
+  else if (status == 0) status = 1;
+  inf.status = status;
+  inf.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  if (status == 3) return fail(PARS3_ENAN, "mrs: NaN or Inf met");
+  if (status == 2) return fail(PARS3_EBREAKDOWN, "mrs: breakdown (gamma = 0)");
+  if (status == 1)
+    return fail(PARS3_ENOCONV, "mrs: relative residual %.3e after %d iterations (tol %.1e)", inf.relres, iters, o.tol);
+  return PARS3_OK;
+}

@@ -62,8 +62,11 @@ __global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tseg_pt
                                              const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_code,
                                              const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
                                              const V *__restrict__ dia, int32_t w_in, int32_t ntiles, int32_t lgT,
-                                             int32_t n, X shift, const X *__restrict__ x, X *__restrict__ y) {
+                                             int32_t n, X shift, const X *__restrict__ x, X *__restrict__ y,
+                                             epilogue<X> ep) {
   __shared__ int32_t s_start[SEGS], s_pre[SEGS + 1], s_code[SEGS];
+  __shared__ double s_red[TB / 64];
+  if (ep.done && *ep.done) return;  // a solver that has finished skips its remaining products
   extern __shared__ unsigned char smem[];
   X *ys = reinterpret_cast<X *>(smem);
   const int32_t t = xcd_tile(blockIdx.x, ntiles);
@@ -142,6 +145,7 @@ __global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tseg_pt
     __syncthreads();  // the segment table is rewritten by the next round
   }
   if (nseg == 0) __syncthreads();
+  double sq = 0.0;
   for (int32_t r = threadIdx.x; r < rows; r += TB) {
     const int64_t i = r0 + r;
     X acc[K];
@@ -164,13 +168,34 @@ __global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tseg_pt
         }
       }
     }
+    if (ep.z) {
+      const X zb = (X)*ep.beta;
 #pragma unroll
-    for (int c = 0; c < K; c++) y[i * K + c] = acc[c];
+      for (int c = 0; c < K; c++) acc[c] += zb * ep.z[i * K + c];
+    }
+#pragma unroll
+    for (int c = 0; c < K; c++) {
+      y[i * K + c] = acc[c];
+      sq += (double)acc[c] * (double)acc[c];
+    }
+  }
+  if (ep.partials) {
+    // partial sum of squares of the tile's outputs, in a fixed order
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) sq += __shfl_xor(sq, d, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < TB / 64; w++) tot += s_red[w];
+      ep.partials[t] = tot;
+    }
   }
 }
 
 template <class V, class X, int K>
-static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shift, const X *x, X *y, hipStream_t s) {
+static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shift, const X *x, X *y, hipStream_t s,
+                           const epilogue<X> &ep) {
   const layout &L = A->lay;
   const int32_t n = (int32_t)A->n;
   if (n == 0) return PARS3_OK;
@@ -178,7 +203,7 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
   k_pair<V, X, K><<<grid, TB, lds, s>>>(L.tseg_ptr.p, L.seg_start.p, L.seg_len.p, L.seg_code.p, L.ent_rc.p, ent_v, in_v,
-                                        L.w_in, L.ntiles, L.lgT, n, shift, x, y);
+                                        L.w_in, L.ntiles, L.lgT, n, shift, x, y, ep);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;
@@ -186,14 +211,16 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
 
 template <class V, class X>
 static pars3_status dispatch_k(pars3_matrix *A, const V *in_v, const V *ent_v, double shift, const void *x, void *y,
-                               int k, hipStream_t s) {
+                               int k, hipStream_t s, const void *epv) {
   const X *xx = (const X *)x;
   X *yy = (X *)y;
+  epilogue<X> ep{};
+  if (epv) ep = *(const epilogue<X> *)epv;
   switch (k) {
-    case 1: return launch<V, X, 1>(A, in_v, ent_v, (X)shift, xx, yy, s);
-    case 2: return launch<V, X, 2>(A, in_v, ent_v, (X)shift, xx, yy, s);
-    case 4: return launch<V, X, 4>(A, in_v, ent_v, (X)shift, xx, yy, s);
-    case 8: return launch<V, X, 8>(A, in_v, ent_v, (X)shift, xx, yy, s);
+    case 1: return launch<V, X, 1>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 2: return launch<V, X, 2>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 4: return launch<V, X, 4>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 8: return launch<V, X, 8>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
     default: return fail(PARS3_EINVAL, "spmv: k must be 1, 2, 4 or 8 (got %d)", k);
   }
 }
@@ -218,20 +245,26 @@ pars3_status prof_mark(pars3_matrix *A, int cls, int stop, hipStream_t s) {
   return PARS3_OK;
 }
 
-pars3_status spmv_rcm(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, hipStream_t s) {
+pars3_status spmv_ex(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, int value_dtype,
+                     hipStream_t s, const void *ep) {
   const layout &L = A->lay;
   if (A->prof.on && A->prof.calls < PROF_MAX) A->prof.calls++;
   if (vec_dtype == PARS3_F64) {
     if (!A->has_f64) return fail(PARS3_ESTATE, "spmv: FP64 values are not stored (value_dtype/keep_fp64)");
-    return dispatch_k<double, double>(A, L.in_f64.p, L.ent_f64.p, shift, x, y, k, s);
+    return dispatch_k<double, double>(A, L.in_f64.p, L.ent_f64.p, shift, x, y, k, s, ep);
   }
   if (vec_dtype == PARS3_F32) {
-    if (A->has_f32) return dispatch_k<float, float>(A, L.in_f32.p, L.ent_f32.p, shift, x, y, k, s);
-    if (A->has_bf16)
-      return dispatch_k<uint16_t, float>(A, L.in_bf16.p, L.ent_bf16.p, shift, x, y, k, s);
+    const bool use32 = A->has_f32 && value_dtype != PARS3_BF16;
+    const bool use16 = A->has_bf16 && value_dtype != PARS3_F32;
+    if (use32) return dispatch_k<float, float>(A, L.in_f32.p, L.ent_f32.p, shift, x, y, k, s, ep);
+    if (use16) return dispatch_k<uint16_t, float>(A, L.in_bf16.p, L.ent_bf16.p, shift, x, y, k, s, ep);
     return fail(PARS3_ESTATE, "spmv: no FP32 or BF16 values are stored for FP32 vectors");
   }
   return fail(PARS3_EINVAL, "spmv: vec_dtype must be PARS3_F64 or PARS3_F32");
+}
+
+pars3_status spmv_rcm(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, hipStream_t s) {
+  return spmv_ex(A, shift, x, y, k, vec_dtype, -1, s, nullptr);
 }
 
 // ------------------------------------------------------------ numbering changes
