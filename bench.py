@@ -45,6 +45,8 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-csr", action="store_true", help="skip the full-CSR comparison")
+    ap.add_argument("--no-mrs", action="store_true", help="skip the MRS time-to-solution runs")
+    ap.add_argument("--mrs-reps", type=int, default=3, help="timed solves per MRS precision")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run 5 plain 1 GiB device copies first (reference for hardware byte counters)")
     args = ap.parse_args(argv)
@@ -196,6 +198,37 @@ def main(argv=None):
         best = min(v["ms"] for v in csr.values())
         out["full_csr"] = {"algorithmic_bytes": Bc, **csr, "best_ms": best, "skew_speedup_vs_best": round(best / ms, 3)}
 
+    # MRS time to an FP64 relative residual of 1e-10 on (0.5 I + S) x = A 1:
+    # FP64-only against mixed precision (FP32 or BF16 inner solves, FP64
+    # refinement); wall time of pars3_mrs_solve, reorder excluded
+    mrs_out = None
+    if not args.no_mrs:
+        alpha = 0.5
+        mrs_out = {"workload": "3D 7-point stencil 128^3, alpha = 0.5, b = A 1, x0 = 0", "tol": 1e-10}
+        ones = torch.ones(n, dtype=torch.float64, device=dev)
+        for name, prec in (("f64", p3.F64), ("f32_refined", p3.F32), ("bf16_refined", p3.BF16)):
+            print(f"[bench] mrs {name}", file=sys.stderr, flush=True)
+            M = p3.Matrix(L).reorder(value_dtype=prec, keep_fp64=int(prec != p3.F64))
+            b = torch.empty_like(ones)
+            p3.pars3_spmv(M.h, alpha, ones, b, 1, p3.F64, p3.ORDER_ORIGINAL)
+            runs = []
+            for r in range(args.mrs_reps + 1):  # the first solve is a warm-up
+                x = torch.zeros_like(ones)
+                torch.cuda.synchronize()
+                st, info, _ = M.mrs(alpha, b, x, order=p3.ORDER_ORIGINAL, tol=1e-10, maxit=20000, precision=prec)
+                if r:
+                    runs.append(info)
+            runs.sort(key=lambda i: i["time_ms"])
+            med = runs[len(runs) // 2]
+            mrs_out[name] = {"ms": round(med["time_ms"], 3), "iters": med["iters"],
+                             "refinements": med["refinements"], "relres": med["relres"],
+                             "us_per_iter": round(1e3 * med["time_ms"] / max(med["iters"], 1), 2),
+                             "min_ms": round(runs[0]["time_ms"], 3)}
+            del M
+        best_mixed = min(mrs_out["f32_refined"]["ms"], mrs_out["bf16_refined"]["ms"])
+        mrs_out["mixed_speedup_vs_f64"] = round(mrs_out["f64"]["ms"] / best_mixed, 3)
+        out["mrs"] = mrs_out
+
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline leg only
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -219,6 +252,18 @@ def main(argv=None):
             "sample": f"{reps} oracle full-CSR FP64 products (plain C, one thread) of the same reordered "
                       f"3D 128^3 matrix; throughput counted with the FP64 skew byte count",
         }
+        if mrs_out is not None:
+            # oracle FP64 MRS: a bounded number of iterations, scaled to the
+            # GPU FP64 solve's iteration count
+            bh = oracle.spmv(L, 0.5, np.ones(n))
+            k = 10
+            t1 = time.perf_counter()
+            oracle.mrs(L, 0.5, bh, tol=0.0, maxit=k)
+            per_it = (time.perf_counter() - t1) / k * 1e3
+            it64 = mrs_out["f64"]["iters"]
+            out["cpu_baseline"]["mrs_ms_per_iter"] = round(per_it, 3)
+            out["cpu_baseline"]["mrs_ms_to_tol_est"] = round(per_it * it64, 1)
+            out["cpu_baseline"]["mrs_sample"] = f"{k} oracle FP64 MRS iterations (one thread), scaled to {it64}"
     print(json.dumps(out), flush=True)
     return 0
 

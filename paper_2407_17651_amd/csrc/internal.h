@@ -163,11 +163,14 @@ struct layout {
   // row tile t owns blocks [tblk_ptr[t], tblk_ptr[t+1]); column tile u is the
   // column tile of blocks ublk[ublk_ptr[u] .. ublk_ptr[u+1]) (ascending)
   dbuf<int32_t> tblk_ptr, ublk_ptr, ublk;
-  // per tile, its segments (row-side blocks, then column-side blocks):
-  // tile t reads segments [tseg_ptr[t], tseg_ptr[t+1]) with entry start
-  // seg_start, length seg_len and code (other tile << 1 | column side)
-  dbuf<int32_t> tseg_ptr, seg_start, seg_len, seg_code;
-  int32_t max_segs = 0;
+  // per tile, its chunks: runs of at most 64 consecutive entries of one
+  // block, its own blocks (row side) first, then the blocks of its column
+  // list (column side).  Tile t reads chunks [tch_ptr[t], tch_ptr[t+1]);
+  // chunk.x = first entry, chunk.y = other tile << 8 | column side << 7 |
+  // (length - 1)
+  dbuf<int32_t> tch_ptr;
+  dbuf<uint2> chunk;
+  int32_t nchunks = 0;
   // layout position of every canonical entry (-1 for inner-band entries)
   dbuf<int32_t> pos_of;
 };

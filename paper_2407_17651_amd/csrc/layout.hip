@@ -182,6 +182,31 @@ __global__ void k_seg_fill(const int32_t *__restrict__ tblk_ptr, const int32_t *
     seg_code[q] = (blk_t[b] << 1) | 1;
   }
 }
+// Chunks: each segment of a tile cut into runs of at most 64 consecutive
+// entries, one per wavefront step of the product.  Descriptor:
+// x = first entry, y = other tile << 8 | column side << 7 | (length - 1).
+__global__ void k_chunk_count(const int32_t *__restrict__ tseg_ptr, const int32_t *__restrict__ seg_len,
+                              int32_t ntiles, int32_t *__restrict__ cnt) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  int32_t c = 0;
+  for (int32_t q = tseg_ptr[t]; q < tseg_ptr[t + 1]; q++) c += (seg_len[q] + 63) >> 6;
+  cnt[t] = c;
+}
+__global__ void k_chunk_fill(const int32_t *__restrict__ tseg_ptr, const int32_t *__restrict__ seg_start,
+                             const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_code,
+                             int32_t ntiles, const int32_t *__restrict__ tch_ptr, uint2 *__restrict__ chunk) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  int32_t c = tch_ptr[t];
+  for (int32_t q = tseg_ptr[t]; q < tseg_ptr[t + 1]; q++) {
+    const uint32_t code = (uint32_t)seg_code[q];  // other tile << 1 | column side
+    for (int32_t off = 0; off < seg_len[q]; off += 64, c++) {
+      const int32_t len = min(64, seg_len[q] - off);
+      chunk[c] = make_uint2((uint32_t)(seg_start[q] + off), (code << 7) | (uint32_t)(len - 1));
+    }
+  }
+}
 __global__ void k_pos_prefix(const int8_t *__restrict__ part, int64_t nnz, int32_t *__restrict__ flag) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < nnz) flag[e] = part[e] != 0;
@@ -264,6 +289,8 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   const int tbits = std::max(1, bits_for((uint64_t)std::max(ntiles - 1, 0)));
   const int key_bits = 2 * tbits + 1 + 2 * lgT;
   if (key_bits > 64) return fail(PARS3_EINVAL, "split: matrix too large for the block key (%d bits)", key_bits);
+  if (ntiles > (1 << 23))
+    return fail(PARS3_EINVAL, "split: %d tiles exceed the chunk descriptor's 2^23; use larger tile_rows", ntiles);
   dbuf<int32_t> kflag, kpos;
   dbuf<uint64_t> k0, k1;
   dbuf<uint32_t> v0, v1;
@@ -336,27 +363,43 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
     k_list_sort<<<nblk(nb), TB, 0, s>>>(L.ublk_ptr.p, ntiles, tmp.p, nb, L.ublk.p);
     P3_LAUNCHED();
   }
-  // per-tile segment tables
+  // per-tile segment tables (temporary), then the chunk lists the product reads
   {
-    dbuf<int32_t> cnt;
+    dbuf<int32_t> cnt, tseg_ptr, seg_start, seg_len, seg_code;
     P3_HIP(cnt.alloc(ntiles));
-    P3_HIP(L.tseg_ptr.alloc(ntiles + 1));
+    P3_HIP(tseg_ptr.alloc(ntiles + 1));
     if (ntiles > 0) {
       k_seg_count<<<nblk(ntiles), TB, 0, s>>>(L.tblk_ptr.p, L.ublk_ptr.p, ntiles, cnt.p);
       P3_LAUNCHED();
     }
-    P3_TRY(scan_i32(cnt.p, L.tseg_ptr.p, ntiles, s));
+    P3_TRY(scan_i32(cnt.p, tseg_ptr.p, ntiles, s));
     int32_t nsegs = 0;
-    P3_HIP(hipMemcpyAsync(&nsegs, L.tseg_ptr.p + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P3_HIP(hipMemcpyAsync(&nsegs, tseg_ptr.p + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     P3_HIP(hipStreamSynchronize(s));
-    P3_HIP(L.seg_start.alloc(nsegs));
-    P3_HIP(L.seg_len.alloc(nsegs));
-    P3_HIP(L.seg_code.alloc(nsegs));
+    P3_HIP(seg_start.alloc(nsegs));
+    P3_HIP(seg_len.alloc(nsegs));
+    P3_HIP(seg_code.alloc(nsegs));
     if (ntiles > 0 && nsegs > 0) {
       k_seg_fill<<<nblk(ntiles), TB, 0, s>>>(L.tblk_ptr.p, L.ublk_ptr.p, L.ublk.p, L.blk_start.p, L.blk_t.p, L.blk_u.p,
-                                             ntiles, L.tseg_ptr.p, L.seg_start.p, L.seg_len.p, L.seg_code.p);
+                                             ntiles, tseg_ptr.p, seg_start.p, seg_len.p, seg_code.p);
+      P3_LAUNCHED();
+      k_chunk_count<<<nblk(ntiles), TB, 0, s>>>(tseg_ptr.p, seg_len.p, ntiles, cnt.p);
+      P3_LAUNCHED();
+    } else if (ntiles > 0) {
+      P3_TRY(fill_i32(cnt.p, 0, ntiles, s));
+    }
+    P3_HIP(L.tch_ptr.alloc(ntiles + 1));
+    P3_TRY(scan_i32(cnt.p, L.tch_ptr.p, ntiles, s));
+    int32_t nch = 0;
+    P3_HIP(hipMemcpyAsync(&nch, L.tch_ptr.p + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P3_HIP(hipStreamSynchronize(s));
+    P3_HIP(L.chunk.alloc(nch));
+    if (ntiles > 0 && nch > 0) {
+      k_chunk_fill<<<nblk(ntiles), TB, 0, s>>>(tseg_ptr.p, seg_start.p, seg_len.p, seg_code.p, ntiles, L.tch_ptr.p,
+                                               L.chunk.p);
       P3_LAUNCHED();
     }
+    L.nchunks = nch;
   }
   // per-tile maxima of blocks (row side and column side), for the read-back
   std::vector<int32_t> ht(ntiles + 1), hu(ntiles + 1);

@@ -17,8 +17,9 @@
 // storing one triangle (Section 3) is kept, while the exchange of conflicting
 // products between owners of different rows (Section 3.1.2) becomes a read of
 // shared data instead of a remote accumulation.
-// Values are FP64, FP32 or BF16; vectors and accumulation are FP64 for FP64
-// values and FP32 otherwise.  k right-hand sides are stored row-major.
+// Values are FP64, FP32 or BF16; vectors are FP64 for FP64 values and FP32
+// otherwise; products are formed in the vector precision and summed in FP64
+// in LDS.  k right-hand sides are stored row-major.
 #include <algorithm>
 
 #include "internal.h"
@@ -26,9 +27,8 @@
 namespace p3 {
 
 static constexpr int TB = 256;
-static constexpr int LDS_MAX = 160 * 1024;
-static constexpr int SEGS = 64;  // segments (blocks) staged per round
-static constexpr int PRE = 4;  // entries per thread whose loads are issued together
+static constexpr size_t LDS_DEFAULT = 64 * 1024;  // dynamic LDS available without an attribute
+static constexpr int PRE = 4;  // chunks per wavefront whose loads are issued together
 
 template <class V>
 struct vload;
@@ -57,18 +57,23 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
   return (b & 7) * per + (b >> 3);
 }
 
+// The tile's work list is a list of chunks, runs of at most 64 consecutive
+// entries of one block.  A wavefront takes whole chunks, so a chunk's
+// descriptor (first entry, length, other tile, side) is uniform over the
+// wavefront and lives in scalar registers: each lane only loads its entry
+// word, value and x element and adds one product into LDS.  Partial sums are
+// kept in FP64 in LDS whatever the vector type (products are formed in the
+// vector precision); LDS adds of FP64 measured faster than of FP32 here.
 template <class V, class X, int K>
-__global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tseg_ptr, const int32_t *__restrict__ seg_start,
-                                             const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_code,
-                                             const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
-                                             const V *__restrict__ dia, int32_t w_in, int32_t ntiles, int32_t lgT,
-                                             int32_t n, X shift, const X *__restrict__ x, X *__restrict__ y,
-                                             epilogue<X> ep) {
-  __shared__ int32_t s_start[SEGS], s_pre[SEGS + 1], s_code[SEGS];
+__global__ __launch_bounds__(TB) void k_tile_product(const int32_t *__restrict__ tch_ptr,
+                                                     const uint2 *__restrict__ chunk,
+                                                     const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
+                                                     const V *__restrict__ dia, int32_t w_in, int32_t ntiles,
+                                                     int32_t lgT, int32_t n, X shift, const X *__restrict__ x,
+                                                     X *__restrict__ y, epilogue<X> ep) {
   __shared__ double s_red[TB / 64];
   if (ep.done && *ep.done) return;  // a solver that has finished skips its remaining products
-  extern __shared__ unsigned char smem[];
-  X *ys = reinterpret_cast<X *>(smem);
+  extern __shared__ double ys[];
   const int32_t t = xcd_tile(blockIdx.x, ntiles);
   if (t >= ntiles) return;
   const int32_t T = 1 << lgT;
@@ -78,79 +83,64 @@ __global__ __launch_bounds__(TB) void k_pair(const int32_t *__restrict__ tseg_pt
   X xown[K];
 #pragma unroll
   for (int c = 0; c < K; c++) xown[c] = (int32_t)threadIdx.x < rows ? x[((int64_t)r0 + threadIdx.x) * K + c] : (X)0;
-  const int32_t g0 = tseg_ptr[t], nseg = tseg_ptr[t + 1] - g0;
-  for (int32_t s = threadIdx.x; s < rows * K; s += TB) ys[s] = (X)0;
-  for (int32_t c0 = 0; c0 < nseg; c0 += SEGS) {
-    const int32_t cnt = min(SEGS, nseg - c0);
-    if (threadIdx.x < 64) {
-      const int lane = threadIdx.x;
-      int32_t len = 0;
-      if (lane < cnt) {
-        s_start[lane] = seg_start[g0 + c0 + lane];
-        s_code[lane] = seg_code[g0 + c0 + lane];
-        len = seg_len[g0 + c0 + lane];
-      }
-      int32_t incl = len;
+  for (int32_t s = threadIdx.x; s < rows * K; s += TB) ys[s] = 0.0;
+  const int32_t c0 = tch_ptr[t], c1 = tch_ptr[t + 1];
+  const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x >> 6);
+  const int32_t lane = threadIdx.x & 63;
+  __syncthreads();
+  for (int32_t cb = c0 + wave; cb < c1; cb += (TB / 64) * PRE) {
+    int32_t slot[PRE], xrow[PRE];
+    X coef[PRE], xv[PRE][K];
 #pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int32_t u = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += u;
-      }
-      s_pre[lane + 1] = incl;
-      if (lane == 0) s_pre[0] = 0;
-    }
-    __syncthreads();
-    const int32_t total = s_pre[cnt];
-    for (int32_t base = 0; base < total; base += PRE * TB) {
-      int32_t slot[PRE], xrow[PRE];
-      X coef[PRE], xv[PRE][K];
-#pragma unroll
-      for (int q = 0; q < PRE; q++) {
-        const int32_t v = base + q * TB + (int32_t)threadIdx.x;
-        slot[q] = -1;
-        xrow[q] = 0;
-        coef[q] = (X)0;
-        if (v < total) {
-          int32_t lo = 0, hi = cnt - 1;  // segment holding v
-          while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (s_pre[mid] <= v) lo = mid;
-            else hi = mid - 1;
-          }
-          const int64_t e = (int64_t)s_start[lo] + (v - s_pre[lo]);
-          const int32_t code = s_code[lo];
-          const int32_t other = code >> 1;
+    for (int q = 0; q < PRE; q++) {
+      const int32_t c = cb + q * (TB / 64);
+      slot[q] = -1;
+      xrow[q] = 0;
+      coef[q] = (X)0;
+      if (c < c1) {
+        const uint2 d = chunk[c];
+        const int32_t len = (int32_t)(d.y & 127u) + 1;
+        const bool col_side = (d.y >> 7) & 1u;
+        const int32_t other = (int32_t)(d.y >> 8);
+        if (lane < len) {
+          const int64_t e = (int64_t)d.x + lane;
           // the column side reads a block first and leaves it in L2; the row
           // side is its last use (nontemporal)
-          const bool col_side = code & 1;
-          const uint32_t rc = col_side ? ent_rc[e] : __builtin_nontemporal_load(ent_rc + e);
-          const X val = col_side ? (X)vload<V>::ld(ent_v, e) : (X)vload<V>::nt(ent_v, e);
+          uint32_t rc;
+          X val;
+          if (col_side) {
+            rc = ent_rc[e];
+            val = (X)vload<V>::ld(ent_v, e);
+          } else {
+            rc = __builtin_nontemporal_load(ent_rc + e);
+            val = (X)vload<V>::nt(ent_v, e);
+          }
           const int32_t ri = (int32_t)(rc >> 16), cj = (int32_t)(rc & 0xffffu);
           slot[q] = col_side ? cj : ri;
           xrow[q] = (other << lgT) + (col_side ? ri : cj);
           coef[q] = col_side ? -val : val;
         }
       }
-#pragma unroll
-      for (int q = 0; q < PRE; q++)
-#pragma unroll
-        for (int c = 0; c < K; c++) xv[q][c] = slot[q] >= 0 ? x[(int64_t)xrow[q] * K + c] : (X)0;
-#pragma unroll
-      for (int q = 0; q < PRE; q++)
-        if (slot[q] >= 0) {
-#pragma unroll
-          for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * K + c], coef[q] * xv[q][c]);
-        }
     }
-    __syncthreads();  // the segment table is rewritten by the next round
+#pragma unroll
+    for (int q = 0; q < PRE; q++)
+#pragma unroll
+      for (int c = 0; c < K; c++) xv[q][c] = slot[q] >= 0 ? x[(int64_t)xrow[q] * K + c] : (X)0;
+#pragma unroll
+    for (int q = 0; q < PRE; q++)
+      if (slot[q] >= 0) {
+#pragma unroll
+        for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * K + c], (double)(coef[q] * xv[q][c]));
+      }
   }
-  if (nseg == 0) __syncthreads();
+  __syncthreads();
   double sq = 0.0;
   for (int32_t r = threadIdx.x; r < rows; r += TB) {
     const int64_t i = r0 + r;
     X acc[K];
 #pragma unroll
-    for (int c = 0; c < K; c++) acc[c] = shift * (r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c]) + ys[r * K + c];
+    for (int c = 0; c < K; c++)
+      acc[c] = shift * (r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c]) + (X)ys[r * K + c];
     for (int32_t k = 1; k <= w_in; k++) {
       const int64_t bse = (int64_t)(k - 1) * n;
       if (i - k >= 0) {
@@ -199,11 +189,20 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   const layout &L = A->lay;
   const int32_t n = (int32_t)A->n;
   if (n == 0) return PARS3_OK;
-  const size_t lds = (size_t)L.T * K * sizeof(X);
+  const size_t lds = (size_t)L.T * K * sizeof(double);
+  if (lds + sizeof(double) * (TB / 64) > LDS_DEFAULT) {
+    // above the default dynamic LDS limit: ask for exactly what is needed
+    static bool raised = false;
+    if (!raised) {
+      P3_HIP(hipFuncSetAttribute((const void *)k_tile_product<V, X, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+      raised = true;
+    }
+  }
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
-  k_pair<V, X, K><<<grid, TB, lds, s>>>(L.tseg_ptr.p, L.seg_start.p, L.seg_len.p, L.seg_code.p, L.ent_rc.p, ent_v, in_v,
-                                        L.w_in, L.ntiles, L.lgT, n, shift, x, y, ep);
+  k_tile_product<V, X, K><<<grid, TB, lds, s>>>(L.tch_ptr.p, L.chunk.p, L.ent_rc.p, ent_v, in_v, L.w_in, L.ntiles,
+                                                L.lgT, n, shift, x, y, ep);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;

@@ -90,6 +90,19 @@ def test_block_right_hand_sides(k, value_dtype):
         assert rel_inf(got[:, c], one) <= TOL[value_dtype]
 
 
+@pytest.mark.parametrize("tile_rows,k", [(1024, 8), (512, 8), (64, 8)])
+def test_block_right_hand_sides_tile_sizes(tile_rows, k):
+    """Largest LDS accumulator (1024 rows x 8 right-hand sides in FP64) and
+    the smallest tiles."""
+    L = synth.rgg2d(30000, 12.0, 17)
+    print(f"[gpu] spmv tile_rows={tile_rows} k={k}", flush=True)
+    perm, B = oracle_reordered(L)
+    M = p3.Matrix(L).reorder(tile_rows=tile_rows)
+    X = synth.vector(L.n, 6, k)
+    got = gpu_spmv(M, -0.5, X, p3.F64)
+    assert rel_inf(got, oracle.spmv(B, -0.5, X)) <= 1e-12
+
+
 def test_original_order():
     L = synth.rgg2d(10000, 10.0, 14)
     M = p3.Matrix(L).reorder()
