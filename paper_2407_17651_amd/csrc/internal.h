@@ -142,6 +142,8 @@ pars3_status fill_u64(uint64_t *p, uint64_t v, int64_t m, hipStream_t s);
 pars3_status iota_i32(int32_t *p, int64_t m, hipStream_t s);
 
 // ---------------------------------------------------------------- stored layouts
+constexpr int CHUNKS_FIXED = 32;          // fixed chunk slots per tile (4 wavefronts x 8)
+constexpr uint32_t CHUNK_EMPTY = 0xffffffffu;
 // One SpMV layout: the three parts of the split arranged for the kernel.
 struct layout {
   int32_t T = 256, lgT = 8, w_in = 0, t_out = 0;
@@ -165,12 +167,14 @@ struct layout {
   dbuf<int32_t> tblk_ptr, ublk_ptr, ublk;
   // per tile, its chunks: runs of at most 64 consecutive entries of one
   // block, its own blocks (row side) first, then the blocks of its column
-  // list (column side).  Tile t reads chunks [tch_ptr[t], tch_ptr[t+1]);
-  // chunk.x = first entry, chunk.y = other tile << 8 | column side << 7 |
-  // (length - 1)
-  dbuf<int32_t> tch_ptr;
-  dbuf<uint2> chunk;
-  int32_t nchunks = 0;
+  // list (column side); chunk.x = first entry, chunk.y = other tile << 8 |
+  // column side << 7 | (length - 1).  The first CHUNKS_FIXED chunks of tile t
+  // sit at chunk_fix[t * CHUNKS_FIXED + q] (CHUNK_EMPTY in .y past the end),
+  // so the product finds them without a pointer load; the rest are
+  // chunk_ovf[ovf_ptr[t] .. ovf_ptr[t+1]).
+  dbuf<uint2> chunk_fix, chunk_ovf;
+  dbuf<int32_t> ovf_ptr;
+  int32_t nchunks = 0, nchunks_ovf = 0;
   // layout position of every canonical entry (-1 for inner-band entries)
   dbuf<int32_t> pos_of;
 };

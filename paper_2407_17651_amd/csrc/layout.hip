@@ -207,6 +207,22 @@ __global__ void k_chunk_fill(const int32_t *__restrict__ tseg_ptr, const int32_t
     }
   }
 }
+__global__ void k_overflow_count(const int32_t *__restrict__ tch_ptr, int32_t ntiles, int32_t *__restrict__ ocnt) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntiles) ocnt[t] = max(0, tch_ptr[t + 1] - tch_ptr[t] - CHUNKS_FIXED);
+}
+// One thread per fixed slot (t, q): slot q < count takes chunk q of tile t,
+// the others the empty marker; slot 0 also moves the tile's overflow chunks.
+__global__ void k_chunk_place(const int32_t *__restrict__ tch_ptr, const uint2 *__restrict__ chunk, int32_t ntiles,
+                              const int32_t *__restrict__ ovf_ptr, uint2 *__restrict__ fix, uint2 *__restrict__ ovf) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)ntiles * CHUNKS_FIXED) return;
+  const int32_t t = (int32_t)(g / CHUNKS_FIXED), q = (int32_t)(g % CHUNKS_FIXED);
+  const int32_t c0 = tch_ptr[t], cnt = tch_ptr[t + 1] - c0;
+  fix[g] = q < cnt ? chunk[c0 + q] : make_uint2(0u, CHUNK_EMPTY);
+  if (q == 0)
+    for (int32_t c = CHUNKS_FIXED; c < cnt; c++) ovf[ovf_ptr[t] + c - CHUNKS_FIXED] = chunk[c0 + c];
+}
 __global__ void k_pos_prefix(const int8_t *__restrict__ part, int64_t nnz, int32_t *__restrict__ flag) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < nnz) flag[e] = part[e] != 0;
@@ -388,18 +404,40 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
     } else if (ntiles > 0) {
       P3_TRY(fill_i32(cnt.p, 0, ntiles, s));
     }
-    P3_HIP(L.tch_ptr.alloc(ntiles + 1));
-    P3_TRY(scan_i32(cnt.p, L.tch_ptr.p, ntiles, s));
+    dbuf<int32_t> tch_ptr, ocnt;
+    dbuf<uint2> chunk;
+    P3_HIP(tch_ptr.alloc(ntiles + 1));
+    P3_TRY(scan_i32(cnt.p, tch_ptr.p, ntiles, s));
     int32_t nch = 0;
-    P3_HIP(hipMemcpyAsync(&nch, L.tch_ptr.p + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P3_HIP(hipMemcpyAsync(&nch, tch_ptr.p + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     P3_HIP(hipStreamSynchronize(s));
-    P3_HIP(L.chunk.alloc(nch));
+    P3_HIP(chunk.alloc(nch));
     if (ntiles > 0 && nch > 0) {
-      k_chunk_fill<<<nblk(ntiles), TB, 0, s>>>(tseg_ptr.p, seg_start.p, seg_len.p, seg_code.p, ntiles, L.tch_ptr.p,
-                                               L.chunk.p);
+      k_chunk_fill<<<nblk(ntiles), TB, 0, s>>>(tseg_ptr.p, seg_start.p, seg_len.p, seg_code.p, ntiles, tch_ptr.p,
+                                               chunk.p);
+      P3_LAUNCHED();
+    }
+    // the first CHUNKS_FIXED chunks of every tile at fixed positions, the
+    // rest in the overflow list
+    P3_HIP(ocnt.alloc(ntiles));
+    P3_HIP(L.ovf_ptr.alloc(ntiles + 1));
+    P3_HIP(L.chunk_fix.alloc((size_t)ntiles * CHUNKS_FIXED));
+    if (ntiles > 0) {
+      k_overflow_count<<<nblk(ntiles), TB, 0, s>>>(tch_ptr.p, ntiles, ocnt.p);
+      P3_LAUNCHED();
+    }
+    P3_TRY(scan_i32(ocnt.p, L.ovf_ptr.p, ntiles, s));
+    int32_t nov = 0;
+    P3_HIP(hipMemcpyAsync(&nov, L.ovf_ptr.p + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P3_HIP(hipStreamSynchronize(s));
+    P3_HIP(L.chunk_ovf.alloc(nov));
+    if (ntiles > 0) {
+      k_chunk_place<<<nblk((int64_t)ntiles * CHUNKS_FIXED), TB, 0, s>>>(tch_ptr.p, chunk.p, ntiles, L.ovf_ptr.p,
+                                                                         L.chunk_fix.p, L.chunk_ovf.p);
       P3_LAUNCHED();
     }
     L.nchunks = nch;
+    L.nchunks_ovf = nov;
   }
   // per-tile maxima of blocks (row side and column side), for the read-back
   std::vector<int32_t> ht(ntiles + 1), hu(ntiles + 1);

@@ -28,7 +28,7 @@ namespace p3 {
 
 static constexpr int TB = 256;
 static constexpr size_t LDS_DEFAULT = 64 * 1024;  // dynamic LDS available without an attribute
-static constexpr int PRE = 4;  // chunks per wavefront whose loads are issued together
+static constexpr int PRE = CHUNKS_FIXED / (TB / 64);  // chunks per wavefront whose loads are issued together
 
 template <class V>
 struct vload;
@@ -64,9 +64,68 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
 // word, value and x element and adds one product into LDS.  Partial sums are
 // kept in FP64 in LDS whatever the vector type (products are formed in the
 // vector precision); LDS adds of FP64 measured faster than of FP32 here.
+// Loads of one group of chunks (one per q) and their products added into
+// the LDS row sums; a descriptor with .y == CHUNK_EMPTY is skipped.
 template <class V, class X, int K>
-__global__ __launch_bounds__(TB) void k_tile_product(const int32_t *__restrict__ tch_ptr,
-                                                     const uint2 *__restrict__ chunk,
+__device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT,
+                                            const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
+                                            const X *__restrict__ x, double *ys) {
+  int32_t slot[PRE], xrow[PRE];
+  X coef[PRE], xv[PRE][K];
+#pragma unroll
+  for (int q = 0; q < PRE; q++) {
+    slot[q] = -1;
+    xrow[q] = 0;
+    coef[q] = (X)0;
+    if (d[q].y != CHUNK_EMPTY) {
+      const int32_t len = (int32_t)(d[q].y & 127u) + 1;
+      const bool col_side = (d[q].y >> 7) & 1u;
+      const int32_t other = (int32_t)(d[q].y >> 8);
+      if (lane < len) {
+        const int64_t e = (int64_t)d[q].x + lane;
+        // the column side reads a block first and leaves it in L2; the row
+        // side is its last use (nontemporal)
+        uint32_t rc;
+        X val;
+        if (col_side) {
+          rc = ent_rc[e];
+          val = (X)vload<V>::ld(ent_v, e);
+        } else {
+          rc = __builtin_nontemporal_load(ent_rc + e);
+          val = (X)vload<V>::nt(ent_v, e);
+        }
+        const int32_t ri = (int32_t)(rc >> 16), cj = (int32_t)(rc & 0xffffu);
+        slot[q] = col_side ? cj : ri;
+        xrow[q] = (other << lgT) + (col_side ? ri : cj);
+        coef[q] = col_side ? -val : val;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PRE; q++)
+#pragma unroll
+    for (int c = 0; c < K; c++) xv[q][c] = slot[q] >= 0 ? x[(int64_t)xrow[q] * K + c] : (X)0;
+#pragma unroll
+  for (int q = 0; q < PRE; q++)
+    if (slot[q] >= 0) {
+#pragma unroll
+      for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * K + c], (double)(coef[q] * xv[q][c]));
+    }
+}
+
+// The tile's work list is a list of chunks, runs of at most 64 consecutive
+// entries of one block.  A wavefront takes whole chunks, so a chunk's
+// descriptor (first entry, length, other tile, side) is uniform over the
+// wavefront and lives in scalar registers: each lane only loads its entry
+// word, value and x element and adds one product into LDS.  The first group
+// of descriptors sits at fixed positions per tile, so its loads depend on
+// nothing.  Partial sums are kept in FP64 in LDS whatever the vector type
+// (products are formed in the vector precision); LDS adds of FP64 measured
+// faster than of FP32 here.
+template <class V, class X, int K>
+__global__ __launch_bounds__(TB) void k_tile_product(const uint2 *__restrict__ chunk_fix,
+                                                     const int32_t *__restrict__ ovf_ptr,
+                                                     const uint2 *__restrict__ chunk_ovf,
                                                      const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
                                                      const V *__restrict__ dia, int32_t w_in, int32_t ntiles,
                                                      int32_t lgT, int32_t n, X shift, const X *__restrict__ x,
@@ -79,59 +138,27 @@ __global__ __launch_bounds__(TB) void k_tile_product(const int32_t *__restrict__
   const int32_t T = 1 << lgT;
   const int32_t r0 = t << lgT;
   const int32_t rows = min(T, n - r0);
-  // x of the thread's first own row, needed at the end, requested first
+  const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x >> 6);
+  const int32_t lane = threadIdx.x & 63;
+  // descriptors of the first group, the overflow range and x of the
+  // thread's first own row are requested before anything else
+  uint2 d[PRE];
+#pragma unroll
+  for (int q = 0; q < PRE; q++) d[q] = chunk_fix[(int64_t)t * CHUNKS_FIXED + wave + q * (TB / 64)];
+  const int32_t o0 = ovf_ptr[t], o1 = ovf_ptr[t + 1];
   X xown[K];
 #pragma unroll
   for (int c = 0; c < K; c++) xown[c] = (int32_t)threadIdx.x < rows ? x[((int64_t)r0 + threadIdx.x) * K + c] : (X)0;
   for (int32_t s = threadIdx.x; s < rows * K; s += TB) ys[s] = 0.0;
-  const int32_t c0 = tch_ptr[t], c1 = tch_ptr[t + 1];
-  const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x >> 6);
-  const int32_t lane = threadIdx.x & 63;
   __syncthreads();
-  for (int32_t cb = c0 + wave; cb < c1; cb += (TB / 64) * PRE) {
-    int32_t slot[PRE], xrow[PRE];
-    X coef[PRE], xv[PRE][K];
+  chunk_group<V, X, K>(d, lane, lgT, ent_rc, ent_v, x, ys);
+  for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
 #pragma unroll
     for (int q = 0; q < PRE; q++) {
       const int32_t c = cb + q * (TB / 64);
-      slot[q] = -1;
-      xrow[q] = 0;
-      coef[q] = (X)0;
-      if (c < c1) {
-        const uint2 d = chunk[c];
-        const int32_t len = (int32_t)(d.y & 127u) + 1;
-        const bool col_side = (d.y >> 7) & 1u;
-        const int32_t other = (int32_t)(d.y >> 8);
-        if (lane < len) {
-          const int64_t e = (int64_t)d.x + lane;
-          // the column side reads a block first and leaves it in L2; the row
-          // side is its last use (nontemporal)
-          uint32_t rc;
-          X val;
-          if (col_side) {
-            rc = ent_rc[e];
-            val = (X)vload<V>::ld(ent_v, e);
-          } else {
-            rc = __builtin_nontemporal_load(ent_rc + e);
-            val = (X)vload<V>::nt(ent_v, e);
-          }
-          const int32_t ri = (int32_t)(rc >> 16), cj = (int32_t)(rc & 0xffffu);
-          slot[q] = col_side ? cj : ri;
-          xrow[q] = (other << lgT) + (col_side ? ri : cj);
-          coef[q] = col_side ? -val : val;
-        }
-      }
+      d[q] = c < o1 ? chunk_ovf[c] : make_uint2(0u, CHUNK_EMPTY);
     }
-#pragma unroll
-    for (int q = 0; q < PRE; q++)
-#pragma unroll
-      for (int c = 0; c < K; c++) xv[q][c] = slot[q] >= 0 ? x[(int64_t)xrow[q] * K + c] : (X)0;
-#pragma unroll
-    for (int q = 0; q < PRE; q++)
-      if (slot[q] >= 0) {
-#pragma unroll
-        for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * K + c], (double)(coef[q] * xv[q][c]));
-      }
+    chunk_group<V, X, K>(d, lane, lgT, ent_rc, ent_v, x, ys);
   }
   __syncthreads();
   double sq = 0.0;
@@ -201,8 +228,8 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   }
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
-  k_tile_product<V, X, K><<<grid, TB, lds, s>>>(L.tch_ptr.p, L.chunk.p, L.ent_rc.p, ent_v, in_v, L.w_in, L.ntiles,
-                                                L.lgT, n, shift, x, y, ep);
+  k_tile_product<V, X, K><<<grid, TB, lds, s>>>(L.chunk_fix.p, L.ovf_ptr.p, L.chunk_ovf.p, L.ent_rc.p, ent_v, in_v,
+                                                L.w_in, L.ntiles, L.lgT, n, shift, x, y, ep);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;
