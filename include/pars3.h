@@ -121,8 +121,8 @@ pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *p, void *s
 /* y = shift*x + S*x  (the shifted skew-symmetric product; Section 1 and eqs.
  * (2)-(6)).  x and y are device arrays of n x k values, row-major (k values of
  * one row are contiguous), k in {1, 2, 4, 8}.  vec_dtype is PARS3_F64 when the
- * stored values are FP64 and PARS3_F32 when they are FP32 or BF16 (FP32
- * accumulation).  order = PARS3_ORDER_RCM: x and y are in the reordered
+ * stored values are FP64 and PARS3_F32 when they are FP32 or BF16 (products
+ * formed in FP32, summed per row in FP64, results rounded to FP32).  order = PARS3_ORDER_RCM: x and y are in the reordered
  * numbering; PARS3_ORDER_ORIGINAL: in the caller's numbering (a gather and a
  * scatter are added).  x and y must not overlap.  Asynchronous.  Errors:
  * ESTATE before pars3_reorder or for a dtype mismatch; EINVAL otherwise. */
@@ -173,6 +173,26 @@ pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x, void *y, 
 pars3_status pars3_csr_get(const pars3_csr *C, int32_t *rowptr, int32_t *col, double *val);
 void pars3_csr_destroy(pars3_csr *C);
 
+/* 32 sparsity features of the reordered lower triangle (after
+ * pars3_reorder): the band profile, spread of distances from the diagonal and
+ * row-length mix that Section 3.1.2 reads off the structure of the reordered
+ * matrix to place the split, as numbers for the configuration selector.  With
+ * b_i = i - first column of row i (0 for an empty row), d = i - j per entry,
+ * beta = max d and l_i the row length:
+ *   f[0] log2 n   f[1] log2 nnz   f[2] nnz/n   f[3] beta/n   f[4] log2(beta+1)
+ *   f[5..9]   nearest-rank p10, p50, p90, p99 and max of b_i, each / beta
+ *   f[10]     nnz / sum b_i
+ *   f[11..18] share of entries with d <= 1, 2, 4, ..., 128
+ *   f[19..21] share of entries with d/beta > 1/2, 3/4, 9/10
+ *   f[22..28] share of rows with l = 0, 1, 2, 3-4, 5-8, 9-16, >= 17
+ *   f[29] max l / mean l   f[30] std(l) / mean(l) (population)
+ *   f[31] share of 256-row tiles whose window (tile end - smallest column of
+ *         the tile) holds at most 160 KiB of FP64 x and y (16 bytes a row)
+ * Ratios with a zero denominator are 0; n = 0 gives all zeros.  Counts are
+ * taken on the GPU; f (host, 32 doubles) is written on return (synchronous,
+ * on the null stream).  Errors: ESTATE before pars3_reorder. */
+pars3_status pars3_features(const pars3_matrix *A, double *f);
+
 /* MRS solver for (alpha*I + S) x = b (Section 1: the minimal-residual method
  * for shifted skew-symmetric systems that motivates the product; each
  * iteration costs one product with S and one inner product).  x_k minimises
@@ -186,7 +206,8 @@ void pars3_csr_destroy(pars3_csr *C);
  * refinement (residual b - A x with FP64 values and vectors) around inner MRS
  * solves whose matrix values are FP32 / BF16 and vectors FP32, with FP64 inner
  * products and scalars; each inner solve reduces its residual by inner_tol
- * (0 = 1e-6 for FP32, 1e-2 for BF16); at most max_refine refinements.  Needs a
+ * (0 = 1e-6 for FP32, 1e-2 for BF16), or by less when less already meets
+ * the outer tolerance; at most max_refine refinements.  Needs a
  * layout built with value_dtype F32 / BF16 and keep_fp64 = 1.
  *
  * Stopping: ||b - A x|| <= tol ||b|| (for FP64, the recurrence's |eta|;

@@ -98,6 +98,7 @@ SIGNATURES = {
     "pars3_csr_spmv": ([_vp, _d, _vp, _vp, _i32, _vp], _st),
     "pars3_csr_get": ([_vp, _vp, _vp, _vp], _st),
     "pars3_csr_destroy": ([_vp], None),
+    "pars3_features": ([_vp, _vp], _st),
     "pars3_mrs_opts_default": ([ctypes.POINTER(MrsOpts)], None),
     "pars3_mrs_solve": ([_vp, _d, _vp, _vp, ctypes.POINTER(MrsOpts), ctypes.POINTER(MrsInfo), _vp], _st),
     "pars3_last_error": ([], ctypes.c_char_p),
@@ -260,6 +261,12 @@ def pars3_csr_destroy(c):
         lib().pars3_csr_destroy(c)
 
 
+def pars3_features(h) -> np.ndarray:
+    f = np.zeros(32, np.float64)
+    _check(lib().pars3_features(h, _ptr(f)), "pars3_features")
+    return f
+
+
 def pars3_mrs_opts_default() -> MrsOpts:
     o = MrsOpts()
     lib().pars3_mrs_opts_default(ctypes.byref(o))
@@ -323,6 +330,9 @@ class Matrix:
         o.hist = hist.ctypes.data if hist_len else None
         st, info = pars3_mrs_solve(self.h, alpha, b, x, o, stream, check)
         return st, info, hist[:min(hist_len, info["iters"])].copy()
+
+    def features(self):
+        return pars3_features(self.h)
 
     def perm(self):
         return pars3_get_perm(self.h, self.n)

@@ -45,23 +45,35 @@ struct mrs_dev {
   int32_t iter, maxit, done, active, status;  // status: 0 ok, 1 maxit, 2 breakdown, 3 nan
 };
 
-__global__ __launch_bounds__(TB) void k_mrs_scalar(mrs_dev *d, int par, const double *__restrict__ partials, int32_t np,
-                                                  double *__restrict__ hist) {
-  __shared__ double red[TB];
+// Sum of the per-tile partials in a fixed order (deterministic): every
+// thread adds a fixed strided subset, then the wavefronts and the workgroup
+// combine in a fixed tree.
+static constexpr int SB = 1024;
+__global__ __launch_bounds__(SB) void k_mrs_scalar(mrs_dev *d, int par, const double *__restrict__ partials,
+                                                  int32_t np, double *__restrict__ hist) {
+  __shared__ double red[SB / 64];
   if (d->done) {
     if (threadIdx.x == 0) d->active = 0;
     return;
   }
-  double sum = 0.0;
-  for (int32_t q = threadIdx.x; q < np; q += TB) sum += partials[q];
-  red[threadIdx.x] = sum;
-  __syncthreads();
-  for (int w = TB / 2; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; u++) {
+    const int32_t q = (int32_t)threadIdx.x + u * SB;
+    v[u] = q < np ? partials[q] : 0.0;
   }
+  for (int32_t q = threadIdx.x + 8 * SB; q < np; q += SB) v[0] += partials[q];
+  double sum = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  sum = threadIdx.x < SB / 64 ? red[threadIdx.x] : 0.0;
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
   if (threadIdx.x != 0) return;
-  const double beta_n = sqrt(red[0]);
+  const double beta_n = sqrt(sum);
   const double beta_j = d->beta[par], c1 = d->c1[par], s1 = d->s1[par], c2 = d->c2[par], s2 = d->s2[par];
   const double eta = d->eta[par], alpha = d->alpha;
   const double eps = s2 * (-beta_j);
@@ -233,7 +245,7 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
       ep.done = &ws.dev.p->done;
       st = spmv_ex(A, 0.0, V[par], W, 1, vec, value_dtype, s, &ep);
       if (st != PARS3_OK) break;
-      k_mrs_scalar<<<1, TB, 0, s>>>(ws.dev.p, par, ws.partials.p, np, hist);
+      k_mrs_scalar<<<1, SB, 0, s>>>(ws.dev.p, par, ws.partials.p, np, hist);
       k_mrs_vec<X><<<std::min<unsigned>(nblk(n), 4096u), TB, 0, s>>>(ws.dev.p, n, V[par], W, P[par], P[par ^ 1], x,
                                                                         V[par ^ 1]);
     }
@@ -426,7 +438,12 @@ extern "C" pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const dou
       P3_LAUNCHED();
       int32_t it = 0, ist = 0;
       double ieta = 0.0;
-      st = mrs_iterate<float>(A, o.precision, alpha, rnorm, bscale, itol * rnorm, budget, o.check_every, ws,
+      // stop the inner solve at the reduction the outer tolerance still
+      // needs (with a margin for the difference between the inner estimate
+      // and the true FP64 residual), never looser than inner_tol
+      const double need = 0.3 * o.tol * bnorm / rnorm;
+      const double itol_now = std::max(itol, need);
+      st = mrs_iterate<float>(A, o.precision, alpha, rnorm, bscale, itol_now * rnorm, budget, o.check_every, ws,
                               (float *)ws.xin.p, s, &it, &ist, &ieta, hist_len > 0 ? ws.hist.p + iters : nullptr);
       if (st != PARS3_OK) return st;
       iters += it;
