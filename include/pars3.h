@@ -173,6 +173,28 @@ pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x, void *y, 
 pars3_status pars3_csr_get(const pars3_csr *C, int32_t *rowptr, int32_t *col, double *val);
 void pars3_csr_destroy(pars3_csr *C);
 
+/* Exhaustive autotuner (Section 3.1.2 leaves the outer bandwidth to the user;
+ * on the GPU the choice also covers the inner band width and the tile
+ * height).  pars3_tune_grid_default writes the default grid for one value
+ * precision into grid[0..cap) and its size into *count (grid may be NULL to
+ * query the size): tile_rows in {64, 128, 256, 512, 1024} x w_in in {0, 1, 2, 4} x
+ * t_out in {paper (-1: beta - 3), -2: half the RCM bandwidth}.
+ * pars3_autotune applies every configuration of grid[0..ngrid) to A (the
+ * reordering is computed once and kept; t_out = -1 and -2 are resolved against
+ * beta, and t_out is raised to w_in where it would fall below it), times
+ * pars3_spmv-equivalent products with k right-hand sides on a fixed vector
+ * (median of three batches of reps products, hipEvents on `stream`), writes
+ * out[g] = {resolved parameters, microseconds per product}, sets *best (may
+ * be NULL) to the fastest index and leaves A split with that configuration.
+ * Synchronous.  Timings are of cache-warm repeated products. */
+typedef struct {
+  pars3_split_params params;
+  double us;
+} pars3_tune_result;
+pars3_status pars3_tune_grid_default(int32_t value_dtype, pars3_split_params *grid, int32_t cap, int32_t *count);
+pars3_status pars3_autotune(pars3_matrix *A, const pars3_split_params *grid, int32_t ngrid, int32_t k, int32_t reps,
+                            pars3_tune_result *out, int32_t *best, void *stream);
+
 /* 32 sparsity features of the reordered lower triangle (after
  * pars3_reorder): the band profile, spread of distances from the diagonal and
  * row-length mix that Section 3.1.2 reads off the structure of the reordered
@@ -247,6 +269,63 @@ typedef struct {
 void pars3_mrs_opts_default(pars3_mrs_opts *o);
 pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, double *x, const pars3_mrs_opts *opts,
                              pars3_mrs_info *info, void *stream);
+
+/* Learned configuration selector: a multilayer perceptron
+ *   x -> ReLU(x W1 + b1) -> ReLU(h1 W2 + b2) -> h2 W3 + b3
+ * from the standardised features (pars3_features) of a reordered matrix to
+ * one predicted log time ratio log(t_g / t_best) per configuration g of a
+ * tuning grid; the argmin is the selection (the paper leaves the outer
+ * bandwidth to be chosen from the bandwidth and density of the reordered
+ * matrix, Section 3.1.2).  FP32 throughout; weights packed W1 [n_in x h1], b1,
+ * W2 [h1 x h2], b2, W3 [h2 x n_out], b3 (input-major).  Training minimises
+ * sum M (out - T)^2 / sum M with Adam.
+ *  create:      He-uniform weights from SplitMix64(seed), zero biases, Adam
+ *               state zero, scaler mean 0 / std 1.
+ *  sizes:       sizes4 = {n_in, h1, h2, n_out}; *n_params (either may be NULL).
+ *  set/get_params, get_grads: host arrays of n_params floats (set_params also
+ *               resets the Adam state and step count).
+ *  set/get_scaler, fit_scaler: feature mean and standard deviation (host
+ *               arrays of n_in floats; fit_scaler computes them from device
+ *               rows X [rows x n_in], population std, 1 where it is 0).
+ *  forward:     out[rows x n_out] (device) for device rows X; standardize = 1
+ *               applies the scaler first.
+ *  loss_grad:   forward and backward on device rows X, targets T and mask M
+ *               ([rows x n_out]); keeps the gradients; *loss (host, may be
+ *               NULL) receives the loss.  Synchronous when loss != NULL.
+ *  adam:        one Adam step with the kept gradients (step count + 1).
+ *  train:       `epochs` passes over device rows X, T, M (scaler applied),
+ *               each over a shuffle (SplitMix64 keys of seed and epoch) cut
+ *               into whole mini-batches of `batch` rows, one Adam step (beta1
+ *               0.9, beta2 0.999, eps 1e-8) per mini-batch; loss_hist (host,
+ *               may be NULL) receives the mean mini-batch loss per epoch.
+ *  select_rows: choice[r] (device) = argmin over the outputs of row r whose
+ *               valid[r][g] > 0 (valid may be NULL: all valid).
+ * pars3_select: features of A on the GPU, the network's choice over grid
+ * (n_out must equal ngrid, n_in 32), and A re-split with that configuration
+ * (t_out resolved as in pars3_autotune); *choice (host, may be NULL) receives
+ * the index.  Synchronous.  The exhaustive pars3_autotune is the fallback when
+ * no trained network is available. */
+typedef struct pars3_mlp pars3_mlp;
+pars3_status pars3_mlp_create(int32_t n_in, int32_t h1, int32_t h2, int32_t n_out, uint64_t seed, pars3_mlp **out);
+void pars3_mlp_destroy(pars3_mlp *m);
+pars3_status pars3_mlp_sizes(const pars3_mlp *m, int32_t *sizes4, int64_t *n_params);
+pars3_status pars3_mlp_set_params(pars3_mlp *m, const float *host);
+pars3_status pars3_mlp_get_params(const pars3_mlp *m, float *host);
+pars3_status pars3_mlp_get_grads(const pars3_mlp *m, float *host);
+pars3_status pars3_mlp_set_scaler(pars3_mlp *m, const float *mean, const float *stdv);
+pars3_status pars3_mlp_get_scaler(const pars3_mlp *m, float *mean, float *stdv);
+pars3_status pars3_mlp_fit_scaler(pars3_mlp *m, const float *X, int32_t rows, void *stream);
+pars3_status pars3_mlp_forward(pars3_mlp *m, const float *X, int32_t rows, int32_t standardize, float *out,
+                               void *stream);
+pars3_status pars3_mlp_loss_grad(pars3_mlp *m, const float *X, const float *T, const float *M, int32_t rows,
+                                 int32_t standardize, double *loss, void *stream);
+pars3_status pars3_mlp_adam(pars3_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
+pars3_status pars3_mlp_train(pars3_mlp *m, const float *X, const float *T, const float *M, int32_t rows,
+                             int32_t batch, int32_t epochs, float lr, uint64_t seed, double *loss_hist, void *stream);
+pars3_status pars3_mlp_select_rows(pars3_mlp *m, const float *X, int32_t rows, const float *valid, int32_t *choice,
+                                   void *stream);
+pars3_status pars3_select(pars3_matrix *A, pars3_mlp *m, const pars3_split_params *grid, int32_t ngrid,
+                          int32_t *choice, void *stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *pars3_last_error(void);

@@ -62,6 +62,10 @@ class Profile(ctypes.Structure):
                 ("ms_other", ctypes.c_double)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("params", SplitParams), ("us", ctypes.c_double)]
+
+
 class MrsOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
@@ -99,6 +103,23 @@ SIGNATURES = {
     "pars3_csr_get": ([_vp, _vp, _vp, _vp], _st),
     "pars3_csr_destroy": ([_vp], None),
     "pars3_features": ([_vp, _vp], _st),
+    "pars3_tune_grid_default": ([_i32, _vp, _i32, ctypes.POINTER(_i32)], _st),
+    "pars3_autotune": ([_vp, _vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32), _vp], _st),
+    "pars3_mlp_create": ([_i32, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)], _st),
+    "pars3_mlp_destroy": ([_vp], None),
+    "pars3_mlp_sizes": ([_vp, _vp, ctypes.POINTER(_i64)], _st),
+    "pars3_mlp_set_params": ([_vp, _vp], _st),
+    "pars3_mlp_get_params": ([_vp, _vp], _st),
+    "pars3_mlp_get_grads": ([_vp, _vp], _st),
+    "pars3_mlp_set_scaler": ([_vp, _vp, _vp], _st),
+    "pars3_mlp_get_scaler": ([_vp, _vp, _vp], _st),
+    "pars3_mlp_fit_scaler": ([_vp, _vp, _i32, _vp], _st),
+    "pars3_mlp_forward": ([_vp, _vp, _i32, _i32, _vp, _vp], _st),
+    "pars3_mlp_loss_grad": ([_vp, _vp, _vp, _vp, _i32, _i32, ctypes.POINTER(_d), _vp], _st),
+    "pars3_mlp_adam": ([_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp], _st),
+    "pars3_mlp_train": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, ctypes.c_float, ctypes.c_uint64, _vp, _vp], _st),
+    "pars3_mlp_select_rows": ([_vp, _vp, _i32, _vp, _vp, _vp], _st),
+    "pars3_select": ([_vp, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp], _st),
     "pars3_mrs_opts_default": ([ctypes.POINTER(MrsOpts)], None),
     "pars3_mrs_solve": ([_vp, _d, _vp, _vp, ctypes.POINTER(MrsOpts), ctypes.POINTER(MrsInfo), _vp], _st),
     "pars3_last_error": ([], ctypes.c_char_p),
@@ -261,6 +282,29 @@ def pars3_csr_destroy(c):
         lib().pars3_csr_destroy(c)
 
 
+def pars3_tune_grid_default(value_dtype=F64):
+    cnt = _i32()
+    _check(lib().pars3_tune_grid_default(int(value_dtype), None, 0, ctypes.byref(cnt)), "pars3_tune_grid_default")
+    grid = (SplitParams * cnt.value)()
+    _check(lib().pars3_tune_grid_default(int(value_dtype), grid, cnt.value, ctypes.byref(cnt)),
+           "pars3_tune_grid_default")
+    return grid
+
+
+def pars3_autotune(h, grid=None, k=1, reps=20, stream=None, value_dtype=F64):
+    """Returns (results, best): results is a list of dicts {w_in, t_out,
+    tile_rows, value_dtype, us}."""
+    if grid is None:
+        grid = pars3_tune_grid_default(value_dtype)
+    out = (TuneResult * len(grid))()
+    best = _i32()
+    _check(lib().pars3_autotune(h, grid, len(grid), int(k), int(reps), out, ctypes.byref(best), _stream(stream)),
+           "pars3_autotune")
+    res = [{"w_in": r.params.w_in, "t_out": r.params.t_out, "tile_rows": r.params.tile_rows,
+            "value_dtype": r.params.value_dtype, "us": r.us} for r in out]
+    return res, best.value
+
+
 def pars3_features(h) -> np.ndarray:
     f = np.zeros(32, np.float64)
     _check(lib().pars3_features(h, _ptr(f)), "pars3_features")
@@ -282,6 +326,115 @@ def pars3_mrs_solve(h, alpha, b, x, opts: MrsOpts | None = None, stream=None, ch
     if check:
         _check(st, "pars3_mrs_solve")
     return st, info.as_dict()
+
+
+class MLP:
+    """Owning wrapper of a ``pars3_mlp`` (the learned configuration selector).
+    Device inputs are float32 torch tensors; parameters move as numpy
+    float32 arrays packed W1, b1, W2, b2, W3, b3 (input-major weights)."""
+
+    NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def __init__(self, n_in=32, h1=64, h2=64, n_out=40, seed=1):
+        h = _vp()
+        _check(lib().pars3_mlp_create(int(n_in), int(h1), int(h2), int(n_out), int(seed), ctypes.byref(h)),
+               "pars3_mlp_create")
+        self.h = h
+        self.sizes = (int(n_in), int(h1), int(h2), int(n_out))
+        npar = _i64()
+        _check(lib().pars3_mlp_sizes(h, None, ctypes.byref(npar)), "pars3_mlp_sizes")
+        self.n_params = npar.value
+
+    def close(self):
+        if self.h:
+            lib().pars3_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shapes(self):
+        n_in, h1, h2, n_out = self.sizes
+        return {"W1": (n_in, h1), "b1": (h1,), "W2": (h1, h2), "b2": (h2,), "W3": (h2, n_out), "b3": (n_out,)}
+
+    def unpack(self, flat):
+        out, o = {}, 0
+        for k, shp in self.shapes().items():
+            m = int(np.prod(shp))
+            out[k] = np.asarray(flat[o:o + m]).reshape(shp)
+            o += m
+        return out
+
+    def pack(self, params):
+        return np.concatenate([np.asarray(params[k], np.float32).ravel() for k in self.NAMES])
+
+    def get_params(self):
+        f = np.zeros(self.n_params, np.float32)
+        _check(lib().pars3_mlp_get_params(self.h, _ptr(f)), "pars3_mlp_get_params")
+        return self.unpack(f)
+
+    def set_params(self, params):
+        f = np.ascontiguousarray(self.pack(params), np.float32)
+        _check(lib().pars3_mlp_set_params(self.h, _ptr(f)), "pars3_mlp_set_params")
+
+    def get_grads(self):
+        f = np.zeros(self.n_params, np.float32)
+        _check(lib().pars3_mlp_get_grads(self.h, _ptr(f)), "pars3_mlp_get_grads")
+        return self.unpack(f)
+
+    def set_scaler(self, mean, std):
+        m = np.ascontiguousarray(mean, np.float32)
+        s = np.ascontiguousarray(std, np.float32)
+        _check(lib().pars3_mlp_set_scaler(self.h, _ptr(m), _ptr(s)), "pars3_mlp_set_scaler")
+
+    def get_scaler(self):
+        m = np.zeros(self.sizes[0], np.float32)
+        s = np.zeros(self.sizes[0], np.float32)
+        _check(lib().pars3_mlp_get_scaler(self.h, _ptr(m), _ptr(s)), "pars3_mlp_get_scaler")
+        return m, s
+
+    def fit_scaler(self, X, stream=None):
+        _check(lib().pars3_mlp_fit_scaler(self.h, _ptr(X), int(X.shape[0]), _stream(stream)), "pars3_mlp_fit_scaler")
+
+    def forward(self, X, standardize=False, stream=None):
+        import torch
+        out = torch.empty((X.shape[0], self.sizes[3]), dtype=torch.float32, device=X.device)
+        _check(lib().pars3_mlp_forward(self.h, _ptr(X), int(X.shape[0]), int(bool(standardize)), _ptr(out),
+                                       _stream(stream)), "pars3_mlp_forward")
+        return out
+
+    def loss_grad(self, X, T, M, standardize=False, stream=None):
+        loss = _d()
+        _check(lib().pars3_mlp_loss_grad(self.h, _ptr(X), _ptr(T), _ptr(M), int(X.shape[0]),
+                                         int(bool(standardize)), ctypes.byref(loss), _stream(stream)),
+               "pars3_mlp_loss_grad")
+        return loss.value
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().pars3_mlp_adam(self.h, float(lr), float(beta1), float(beta2), float(eps), _stream(stream)),
+               "pars3_mlp_adam")
+
+    def train(self, X, T, M, batch=128, epochs=100, lr=1e-3, seed=1, stream=None):
+        hist = np.zeros(max(int(epochs), 1), np.float64)
+        _check(lib().pars3_mlp_train(self.h, _ptr(X), _ptr(T), _ptr(M), int(X.shape[0]), int(batch), int(epochs),
+                                     float(lr), int(seed), _ptr(hist), _stream(stream)), "pars3_mlp_train")
+        return hist[:epochs]
+
+    def select_rows(self, X, valid=None, stream=None):
+        import torch
+        choice = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+        _check(lib().pars3_mlp_select_rows(self.h, _ptr(X), int(X.shape[0]), _ptr(valid), _ptr(choice),
+                                           _stream(stream)), "pars3_mlp_select_rows")
+        return choice
+
+
+def pars3_select(h, mlp: MLP, grid, stream=None) -> int:
+    c = _i32()
+    _check(lib().pars3_select(h, mlp.h, grid, len(grid), ctypes.byref(c), _stream(stream)), "pars3_select")
+    return c.value
 
 
 # ------------------------------------------------------------------ convenience wrapper

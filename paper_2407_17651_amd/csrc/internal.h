@@ -25,9 +25,9 @@ void clear_error();
     }                                                                                                     \
   } while (0)
 
-#define P3_TRY(expr)                     \
+#define P3_TRY(...)                      \
   do {                                   \
-    pars3_status s_ = (expr);            \
+    pars3_status s_ = (__VA_ARGS__);     \
     if (s_ != PARS3_OK) return s_;       \
   } while (0)
 
