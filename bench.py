@@ -35,6 +35,77 @@ def skew_bytes(n, nnz, dtype, k=1):
     return nnz * (sv + 4) + (n + 1) * 4 + n * k * (sx + sx)
 
 
+def batched(args, p3, synth, torch, np):
+    """256 skew matrices (2D/3D stencils and random geometric graphs, n
+    log-uniform in [2k, 200k]) with k = 8 FP32 right-hand sides in one
+    persistent graph-captured launch, configurations chosen per matrix by the
+    trained selector when its weights are present (else the defaults); then
+    256 MRS solves (alpha_i in [0.1, 2], b_i = A_i 1) to 1e-10 together."""
+    from paper_2407_17651_amd import selector
+
+    specs = synth.batch_specs(256)
+    print("[bench] batched: generating 256 matrices", file=sys.stderr, flush=True)
+    Ls = [synth.make(s, "uniform_f32") for s in specs]
+    net, grid = selector.load_trained(p3) if os.path.exists(selector.WEIGHTS) else (None, None)
+    t0 = time.perf_counter()
+    mats, chosen = [], []
+    for L in Ls:
+        M = p3.Matrix(L)
+        if net is not None:
+            M.reorder(value_dtype=p3.F32, keep_fp64=1)
+            chosen.append(p3.pars3_select(M.h, net, grid))
+            # pars3_select re-split with FP32 values only: keep FP64 for MRS
+            i = M.info()
+            M.reorder(value_dtype=p3.F32, keep_fp64=1, tile_rows=i["tile_rows"], w_in=i["w_in"], t_out=i["t_out"])
+        else:
+            M.reorder(value_dtype=p3.F32, keep_fp64=1)
+        mats.append(M)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    bat = p3.Batch(mats)
+    dev = torch.device("cuda:0")
+    xs = [torch.from_numpy(synth.vector(L.n, 500 + i, 8)).to(dev, torch.float32) for i, L in enumerate(Ls)]
+    ys = [torch.empty_like(x) for x in xs]
+    shifts = np.array([s["alpha"] for s in specs])
+    for _ in range(5):
+        bat.spmv(xs, ys, shifts, k=8, vec_dtype=p3.F32)
+    torch.cuda.synchronize()
+    reps = max(10, args.steps // 4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bat.spmv(xs, ys, shifts, k=8, vec_dtype=p3.F32)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nsum = sum(L.n for L in Ls)
+    nnzsum = sum(L.nnz for L in Ls)
+    Bb = sum(skew_bytes(L.n, L.nnz, "f32", 8) for L in Ls)
+    out = {"workload": "256 skew matrices (2D/3D stencils, RGG deg 16), n log-uniform in [2k, 200k], "
+                       "k = 8 FP32 right-hand sides, one persistent graph-captured launch",
+           "sum_n": nsum, "sum_nnz_lower": nnzsum, "configs": "selector" if net is not None else "default",
+           "ms_per_launch": round(ms, 4), "gbs": round(Bb / (ms * 1e-3) / 1e9, 1),
+           "gflops": round(4.0 * 8 * nnzsum / (ms * 1e-3) / 1e9, 1), "prep_s": round(prep_s, 2)}
+    if chosen:
+        out["selector_choices"] = {str(k): int(v) for k, v in zip(*np.unique(chosen, return_counts=True))}
+    # batched MRS
+    ones = [torch.ones(L.n, dtype=torch.float64, device=dev) for L in Ls]
+    bs = [torch.empty_like(o) for o in ones]
+    for i, M in enumerate(mats):
+        p3.pars3_spmv(M.h, float(shifts[i]), ones[i], bs[i], 1, p3.F64, p3.ORDER_RCM)
+    xs0 = [torch.zeros_like(o) for o in ones]
+    print("[bench] batched MRS", file=sys.stderr, flush=True)
+    st, infos = bat.mrs(shifts, bs, xs0, check=False, order=p3.ORDER_RCM, tol=1e-10, maxit=20000)
+    for x in xs0:
+        x.zero_()
+    st, infos = bat.mrs(shifts, bs, xs0, check=False, order=p3.ORDER_RCM, tol=1e-10, maxit=20000)
+    it = np.array([i["iters"] for i in infos])
+    out["mrs"] = {"status": p3.STATUS_NAMES[st], "ms": round(infos[0]["time_ms"], 2),
+                  "max_relres": float(max(i["relres"] for i in infos)), "iters_max": int(it.max()),
+                  "iters_mean": round(float(it.mean()), 1), "systems": len(infos)}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +118,7 @@ def main(argv=None):
     ap.add_argument("--no-csr", action="store_true", help="skip the full-CSR comparison")
     ap.add_argument("--no-mrs", action="store_true", help="skip the MRS time-to-solution runs")
     ap.add_argument("--mrs-reps", type=int, default=3, help="timed solves per MRS precision")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run 5 plain 1 GiB device copies first (reference for hardware byte counters)")
     args = ap.parse_args(argv)
@@ -228,6 +300,9 @@ def main(argv=None):
         best_mixed = min(mrs_out["f32_refined"]["ms"], mrs_out["bf16_refined"]["ms"])
         mrs_out["mixed_speedup_vs_f64"] = round(mrs_out["f64"]["ms"] / best_mixed, 3)
         out["mrs"] = mrs_out
+
+    if not args.no_batch:
+        out["batched"] = batched(args, p3, synth, torch, np)
 
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline leg only

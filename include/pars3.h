@@ -270,6 +270,39 @@ void pars3_mrs_opts_default(pars3_mrs_opts *o);
 pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, double *x, const pars3_mrs_opts *opts,
                              pars3_mrs_info *info, void *stream);
 
+/* Batches of matrices (independent systems of uneven sizes), each reordered
+ * and split with its own configuration, processed together: one persistent
+ * launch per product walks a work list of (matrix, tile) items split into 8
+ * per-XCD queues of equal estimated cost (matrices largest first, tiles
+ * ascending); each launch is captured in a hipGraph and replayed.
+ *  pars3_batch_create: m reordered handles (the batch keeps pointers to them;
+ *    they must outlive it and must not be re-split while it exists).
+ *  pars3_batch_info: number of items, persistent grid size and the 9 queue
+ *    boundaries (host outputs, each may be NULL).
+ *  pars3_batch_spmv: y_i = shifts[i] x_i + S_i x_i for every matrix i, with
+ *    host arrays x[m], y[m] of device pointers (n_i x k row-major vectors in
+ *    matrix i's reordered numbering, k in {1, 2, 4, 8}); shifts (host, m) may
+ *    be NULL (all zero); vec_dtype and value_dtype as in pars3_spmv (every
+ *    matrix must store the values used).  The launch is captured once per
+ *    distinct (pointers, shifts, k, dtype) and replayed while they repeat.
+ *    Asynchronous on `stream`.
+ *  pars3_batch_mrs_solve: MRS for (alphas[i] I + S_i) x_i = b_i for every i
+ *    (host arrays of m device pointers to FP64 vectors; x holds x0 on entry),
+ *    FP64 iterations (opts->precision must be PARS3_F64; FP64 values
+ *    needed), all systems advanced together by one persistent product, one
+ *    scalar kernel and one vector kernel per iteration (systems that have
+ *    converged are skipped), two iterations per graph replay.  infos (host, m,
+ *    may be NULL) per system; time_ms is the whole batch's.  Returns the worst
+ *    status (ENOCONV, EBREAKDOWN, ENAN) if any system fails.  Synchronous. */
+typedef struct pars3_batch pars3_batch;
+pars3_status pars3_batch_create(int32_t m, pars3_matrix *const *mats, pars3_batch **out);
+void pars3_batch_destroy(pars3_batch *B);
+pars3_status pars3_batch_info(const pars3_batch *B, int32_t *n_items, int32_t *grid, int32_t *queue_begin9);
+pars3_status pars3_batch_spmv(pars3_batch *B, const double *shifts, const void *const *x, void *const *y, int32_t k,
+                              int32_t vec_dtype, int32_t value_dtype, void *stream);
+pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alphas, const double *const *b, double *const *x,
+                                   const pars3_mrs_opts *opts, pars3_mrs_info *infos, void *stream);
+
 /* Learned configuration selector: a multilayer perceptron
  *   x -> ReLU(x W1 + b1) -> ReLU(h1 W2 + b2) -> h2 W3 + b3
  * from the standardised features (pars3_features) of a reordered matrix to

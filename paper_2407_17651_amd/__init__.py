@@ -105,6 +105,11 @@ SIGNATURES = {
     "pars3_features": ([_vp, _vp], _st),
     "pars3_tune_grid_default": ([_i32, _vp, _i32, ctypes.POINTER(_i32)], _st),
     "pars3_autotune": ([_vp, _vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32), _vp], _st),
+    "pars3_batch_create": ([_i32, _vp, ctypes.POINTER(_vp)], _st),
+    "pars3_batch_destroy": ([_vp], None),
+    "pars3_batch_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _vp], _st),
+    "pars3_batch_spmv": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp], _st),
+    "pars3_batch_mrs_solve": ([_vp, _vp, _vp, _vp, ctypes.POINTER(MrsOpts), _vp, _vp], _st),
     "pars3_mlp_create": ([_i32, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)], _st),
     "pars3_mlp_destroy": ([_vp], None),
     "pars3_mlp_sizes": ([_vp, _vp, ctypes.POINTER(_i64)], _st),
@@ -429,6 +434,57 @@ class MLP:
         _check(lib().pars3_mlp_select_rows(self.h, _ptr(X), int(X.shape[0]), _ptr(valid), _ptr(choice),
                                            _stream(stream)), "pars3_mlp_select_rows")
         return choice
+
+
+class Batch:
+    """Owning wrapper of a ``pars3_batch`` over reordered ``Matrix`` objects
+    (kept alive by the batch)."""
+
+    def __init__(self, mats):
+        self.mats = list(mats)
+        arr = (_vp * len(self.mats))(*[m.h for m in self.mats])
+        h = _vp()
+        _check(lib().pars3_batch_create(len(self.mats), arr, ctypes.byref(h)), "pars3_batch_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().pars3_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        ni, g = _i32(), _i32()
+        qb = np.zeros(9, np.int32)
+        _check(lib().pars3_batch_info(self.h, ctypes.byref(ni), ctypes.byref(g), _ptr(qb)), "pars3_batch_info")
+        return {"n_items": ni.value, "grid": g.value, "queues": qb}
+
+    def spmv(self, xs, ys, shifts=None, k=1, vec_dtype=F64, value_dtype=-1, stream=None):
+        m = len(self.mats)
+        xa = (_vp * m)(*[_ptr(x) for x in xs])
+        ya = (_vp * m)(*[_ptr(y) for y in ys])
+        sh = None if shifts is None else np.ascontiguousarray(shifts, np.float64)
+        _check(lib().pars3_batch_spmv(self.h, _ptr(sh), xa, ya, int(k), int(vec_dtype), int(value_dtype),
+                                      _stream(stream)), "pars3_batch_spmv")
+
+    def mrs(self, alphas, bs, xs, check=True, stream=None, **kw):
+        m = len(self.mats)
+        o = pars3_mrs_opts_default()
+        for k, v in kw.items():
+            setattr(o, k, type(getattr(o, k))(v))
+        al = np.ascontiguousarray(alphas, np.float64)
+        ba = (_vp * m)(*[_ptr(b) for b in bs])
+        xa = (_vp * m)(*[_ptr(x) for x in xs])
+        infos = (MrsInfo * m)()
+        st = int(lib().pars3_batch_mrs_solve(self.h, _ptr(al), ba, xa, ctypes.byref(o), infos, _stream(stream)))
+        if check:
+            _check(st, "pars3_batch_mrs_solve")
+        return st, [i.as_dict() for i in infos]
 
 
 def pars3_select(h, mlp: MLP, grid, stream=None) -> int:

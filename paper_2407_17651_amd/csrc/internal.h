@@ -240,6 +240,91 @@ struct epilogue {
   double *partials = nullptr;
   const int32_t *done = nullptr;
 };
+// Device state of one MRS run.  Rotation state is double-buffered by
+// iteration parity: iteration j reads slot j&1 and writes slot (j+1)&1.
+struct mrs_dev {
+  double beta[2], c1[2], s1[2], c2[2], s2[2], eta[2];
+  double delta, eps, gamma, ceta, inv_beta;  // this iteration, for k_mrs_vec
+  double bnorm, tol_abs, alpha, minus_one;
+  int32_t iter, maxit, done, active, status;  // status: 0 ok, 1 maxit, 2 breakdown, 3 nan
+};
+
+// One step of the rotation recurrence from ||w||^2 (see mrs.hip); run by
+// one thread.  Sets the coefficients of this iteration's vector update
+// (active = 1) or stops the run (done = 1, status).
+__device__ __forceinline__ void mrs_update(mrs_dev *d, int par, double sumsq, double *hist) {
+  const double beta_n = sqrt(sumsq);
+  const double beta_j = d->beta[par], c1 = d->c1[par], s1 = d->s1[par], c2 = d->c2[par], s2 = d->s2[par];
+  const double eta = d->eta[par], alpha = d->alpha;
+  const double eps = s2 * (-beta_j);
+  const double dbar = c2 * (-beta_j);
+  const double delta = c1 * dbar + s1 * alpha;
+  const double gbar = -s1 * dbar + c1 * alpha;
+  const double gamma = sqrt(gbar * gbar + beta_n * beta_n);
+  if (!isfinite(beta_n) || !isfinite(gamma)) {
+    d->status = 3;
+    d->done = 1;
+    d->active = 0;
+    return;
+  }
+  if (gamma == 0.0) {
+    d->status = 2;
+    d->done = 1;
+    d->active = 0;
+    return;
+  }
+  const double c = gbar / gamma, s = beta_n / gamma;
+  d->delta = delta;
+  d->eps = eps;
+  d->gamma = gamma;
+  d->ceta = c * eta;
+  d->inv_beta = beta_n > 0.0 ? 1.0 / beta_n : 0.0;
+  d->active = 1;
+  const double eta_n = -s * eta;
+  const int32_t it = d->iter + 1;
+  d->iter = it;
+  if (hist) hist[it - 1] = fabs(eta_n) / d->bnorm;
+  const int q = par ^ 1;
+  d->beta[q] = beta_n;
+  d->c1[q] = c;
+  d->s1[q] = s;
+  d->c2[q] = c1;
+  d->s2[q] = s1;
+  d->eta[q] = eta_n;
+  if (fabs(eta_n) <= d->tol_abs || beta_n == 0.0) {
+    d->done = 1;
+  } else if (it >= d->maxit) {
+    d->done = 1;
+    d->status = 1;
+  }
+}
+
+// One product task as the product kernels read it: a matrix layout, its
+// value arrays (type given separately), the vectors and the epilogue.
+struct prod_task {
+  const uint2 *chunk_fix;
+  const int32_t *ovf_ptr;
+  const uint2 *chunk_ovf;
+  const uint32_t *ent_rc;
+  const void *ent_v, *dia;
+  int32_t w_in, ntiles, lgT, n;
+  double shift;
+  const void *x;
+  void *y;
+  const void *z;
+  const double *beta;
+  double *partials;
+  const int32_t *done;
+};
+// Fills the layout and value fields of a task for products with vectors of
+// vec_dtype (value_dtype picks FP32 or BF16 values when both are stored, -1:
+// whichever is stored); *vkind receives the value type used.
+pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, prod_task *a, int *vkind);
+// Persistent product over many tasks: items (task, tile) in 8 queues
+// [qbeg[q], qbeg[q+1]), counters qctr[8] (cleared here by a fill kernel).
+// maxT: the largest tile height among the tasks.
+pars3_status launch_batch(int vkind, int k, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
+                          int32_t *qctr, int32_t grid, int32_t maxT, hipStream_t s);
 // Product with an optional epilogue; value_dtype selects FP32 or BF16 values
 // when both are stored (-1: whichever is stored).
 pars3_status spmv_ex(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, int value_dtype,

@@ -36,15 +36,6 @@ namespace p3 {
 static constexpr int TB = 256;
 static inline unsigned nblk(int64_t m) { return (unsigned)std::max<int64_t>(1, cdiv(m, TB)); }
 
-// Device state of one MRS run.  Rotation state is double-buffered by
-// iteration parity: iteration j reads slot j&1 and writes slot (j+1)&1.
-struct mrs_dev {
-  double beta[2], c1[2], s1[2], c2[2], s2[2], eta[2];
-  double delta, eps, gamma, ceta, inv_beta;  // this iteration, for k_mrs_vec
-  double bnorm, tol_abs, alpha, minus_one;
-  int32_t iter, maxit, done, active, status;  // status: 0 ok, 1 maxit, 2 breakdown, 3 nan
-};
-
 // Sum of the per-tile partials in a fixed order (deterministic): every
 // thread adds a fixed strided subset, then the wavefronts and the workgroup
 // combine in a fixed tree.
@@ -73,50 +64,7 @@ __global__ __launch_bounds__(SB) void k_mrs_scalar(mrs_dev *d, int par, const do
 #pragma unroll
   for (int off = 8; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
   if (threadIdx.x != 0) return;
-  const double beta_n = sqrt(sum);
-  const double beta_j = d->beta[par], c1 = d->c1[par], s1 = d->s1[par], c2 = d->c2[par], s2 = d->s2[par];
-  const double eta = d->eta[par], alpha = d->alpha;
-  const double eps = s2 * (-beta_j);
-  const double dbar = c2 * (-beta_j);
-  const double delta = c1 * dbar + s1 * alpha;
-  const double gbar = -s1 * dbar + c1 * alpha;
-  const double gamma = sqrt(gbar * gbar + beta_n * beta_n);
-  if (!isfinite(beta_n) || !isfinite(gamma)) {
-    d->status = 3;
-    d->done = 1;
-    d->active = 0;
-    return;
-  }
-  if (gamma == 0.0) {
-    d->status = 2;
-    d->done = 1;
-    d->active = 0;
-    return;
-  }
-  const double c = gbar / gamma, s = beta_n / gamma;
-  d->delta = delta;
-  d->eps = eps;
-  d->gamma = gamma;
-  d->ceta = c * eta;
-  d->inv_beta = beta_n > 0.0 ? 1.0 / beta_n : 0.0;
-  d->active = 1;
-  const double eta_n = -s * eta;
-  const int32_t it = d->iter + 1;
-  d->iter = it;
-  if (hist) hist[it - 1] = fabs(eta_n) / d->bnorm;
-  const int q = par ^ 1;
-  d->beta[q] = beta_n;
-  d->c1[q] = c;
-  d->s1[q] = s;
-  d->c2[q] = c1;
-  d->s2[q] = s1;
-  d->eta[q] = eta_n;
-  if (fabs(eta_n) <= d->tol_abs || beta_n == 0.0) {
-    d->done = 1;
-  } else if (it >= d->maxit) {
-    d->done = 1;
-    d->status = 1;
-  }
+  mrs_update(d, par, sum, hist);
 }
 
 template <class X>

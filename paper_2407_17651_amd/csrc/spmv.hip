@@ -57,13 +57,6 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
   return (b & 7) * per + (b >> 3);
 }
 
-// The tile's work list is a list of chunks, runs of at most 64 consecutive
-// entries of one block.  A wavefront takes whole chunks, so a chunk's
-// descriptor (first entry, length, other tile, side) is uniform over the
-// wavefront and lives in scalar registers: each lane only loads its entry
-// word, value and x element and adds one product into LDS.  Partial sums are
-// kept in FP64 in LDS whatever the vector type (products are formed in the
-// vector precision); LDS adds of FP64 measured faster than of FP32 here.
 // Loads of one group of chunks (one per q) and their products added into
 // the LDS row sums; a descriptor with .y == CHUNK_EMPTY is skipped.
 template <class V, class X, int K>
@@ -121,20 +114,16 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
 // of descriptors sits at fixed positions per tile, so its loads depend on
 // nothing.  Partial sums are kept in FP64 in LDS whatever the vector type
 // (products are formed in the vector precision); LDS adds of FP64 measured
-// faster than of FP32 here.
+// faster than of FP32 here.  Called by every thread of the workgroup.
 template <class V, class X, int K>
-__global__ __launch_bounds__(TB) void k_tile_product(const uint2 *__restrict__ chunk_fix,
-                                                     const int32_t *__restrict__ ovf_ptr,
-                                                     const uint2 *__restrict__ chunk_ovf,
-                                                     const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
-                                                     const V *__restrict__ dia, int32_t w_in, int32_t ntiles,
-                                                     int32_t lgT, int32_t n, X shift, const X *__restrict__ x,
-                                                     X *__restrict__ y, epilogue<X> ep) {
-  __shared__ double s_red[TB / 64];
-  if (ep.done && *ep.done) return;  // a solver that has finished skips its remaining products
-  extern __shared__ double ys[];
-  const int32_t t = xcd_tile(blockIdx.x, ntiles);
-  if (t >= ntiles) return;
+__device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double *ys, double *s_red) {
+  const V *__restrict__ ent_v = (const V *)a.ent_v;
+  const V *__restrict__ dia = (const V *)a.dia;
+  const X *__restrict__ x = (const X *)a.x;
+  X *__restrict__ y = (X *)a.y;
+  const X *__restrict__ z = (const X *)a.z;
+  const int32_t n = a.n, lgT = a.lgT, w_in = a.w_in;
+  const X shift = (X)a.shift;
   const int32_t T = 1 << lgT;
   const int32_t r0 = t << lgT;
   const int32_t rows = min(T, n - r0);
@@ -144,21 +133,21 @@ __global__ __launch_bounds__(TB) void k_tile_product(const uint2 *__restrict__ c
   // thread's first own row are requested before anything else
   uint2 d[PRE];
 #pragma unroll
-  for (int q = 0; q < PRE; q++) d[q] = chunk_fix[(int64_t)t * CHUNKS_FIXED + wave + q * (TB / 64)];
-  const int32_t o0 = ovf_ptr[t], o1 = ovf_ptr[t + 1];
+  for (int q = 0; q < PRE; q++) d[q] = a.chunk_fix[(int64_t)t * CHUNKS_FIXED + wave + q * (TB / 64)];
+  const int32_t o0 = a.ovf_ptr[t], o1 = a.ovf_ptr[t + 1];
   X xown[K];
 #pragma unroll
   for (int c = 0; c < K; c++) xown[c] = (int32_t)threadIdx.x < rows ? x[((int64_t)r0 + threadIdx.x) * K + c] : (X)0;
   for (int32_t s = threadIdx.x; s < rows * K; s += TB) ys[s] = 0.0;
   __syncthreads();
-  chunk_group<V, X, K>(d, lane, lgT, ent_rc, ent_v, x, ys);
+  chunk_group<V, X, K>(d, lane, lgT, a.ent_rc, ent_v, x, ys);
   for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
 #pragma unroll
     for (int q = 0; q < PRE; q++) {
       const int32_t c = cb + q * (TB / 64);
-      d[q] = c < o1 ? chunk_ovf[c] : make_uint2(0u, CHUNK_EMPTY);
+      d[q] = c < o1 ? a.chunk_ovf[c] : make_uint2(0u, CHUNK_EMPTY);
     }
-    chunk_group<V, X, K>(d, lane, lgT, ent_rc, ent_v, x, ys);
+    chunk_group<V, X, K>(d, lane, lgT, a.ent_rc, ent_v, x, ys);
   }
   __syncthreads();
   double sq = 0.0;
@@ -185,10 +174,10 @@ __global__ __launch_bounds__(TB) void k_tile_product(const uint2 *__restrict__ c
         }
       }
     }
-    if (ep.z) {
-      const X zb = (X)*ep.beta;
+    if (z) {
+      const X zb = (X)*a.beta;
 #pragma unroll
-      for (int c = 0; c < K; c++) acc[c] += zb * ep.z[i * K + c];
+      for (int c = 0; c < K; c++) acc[c] += zb * z[i * K + c];
     }
 #pragma unroll
     for (int c = 0; c < K; c++) {
@@ -196,18 +185,63 @@ __global__ __launch_bounds__(TB) void k_tile_product(const uint2 *__restrict__ c
       sq += (double)acc[c] * (double)acc[c];
     }
   }
-  if (ep.partials) {
+  if (a.partials) {
     // partial sum of squares of the tile's outputs, in a fixed order
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) sq += __shfl_xor(sq, d, 64);
+    for (int d2 = 32; d2 >= 1; d2 >>= 1) sq += __shfl_xor(sq, d2, 64);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = sq;
     __syncthreads();
     if (threadIdx.x == 0) {
       double tot = 0.0;
       for (int w = 0; w < TB / 64; w++) tot += s_red[w];
-      ep.partials[t] = tot;
+      a.partials[t] = tot;
     }
   }
+}
+
+// One matrix: one workgroup per tile.
+template <class V, class X, int K>
+__global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
+  __shared__ double s_red[TB / 64];
+  extern __shared__ double ys[];
+  if (a.done && *a.done) return;  // a solver that has finished skips its remaining products
+  const int32_t t = xcd_tile(blockIdx.x, a.ntiles);
+  if (t >= a.ntiles) return;
+  tile_body<V, X, K>(a, t, ys, s_red);
+}
+
+// Many matrices in one launch: persistent workgroups take (matrix, tile)
+// items from the queue of their XCD (workgroup b runs on XCD b % 8) with one
+// atomic per item, until the queue is empty; no workgroup waits for another.
+// Items of a matrix whose solver has finished are skipped.
+template <class V, class X, int K>
+__global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restrict__ tasks,
+                                                      const int2 *__restrict__ items,
+                                                      const int32_t *__restrict__ qbeg, int32_t *__restrict__ qctr) {
+  __shared__ double s_red[TB / 64];
+  __shared__ int32_t s_item;
+  extern __shared__ double ys[];
+  const int q = blockIdx.x & 7;
+  const int32_t end = qbeg[q + 1];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = qbeg[q] + atomicAdd(&qctr[q], 1);
+    __syncthreads();
+    const int32_t it = s_item;
+    __syncthreads();  // every thread has read s_item before it is replaced
+    if (it >= end) break;
+    const int2 w = items[it];
+    const prod_task &a = tasks[w.x];
+    if (a.done && *a.done) continue;
+    tile_body<V, X, K>(a, w.y, ys, s_red);
+    __syncthreads();  // ys and s_red are reused by the next item
+  }
+}
+
+template <class F>
+static pars3_status raise_lds(F *kernel, size_t lds) {
+  if (lds + sizeof(double) * (TB / 64) + 64 > LDS_DEFAULT)
+    P3_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  return PARS3_OK;
 }
 
 template <class V, class X, int K>
@@ -217,19 +251,32 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   const int32_t n = (int32_t)A->n;
   if (n == 0) return PARS3_OK;
   const size_t lds = (size_t)L.T * K * sizeof(double);
-  if (lds + sizeof(double) * (TB / 64) > LDS_DEFAULT) {
-    // above the default dynamic LDS limit: ask for exactly what is needed
-    static bool raised = false;
-    if (!raised) {
-      P3_HIP(hipFuncSetAttribute((const void *)k_tile_product<V, X, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds));
-      raised = true;
-    }
+  static bool raised = false;  // above the default dynamic LDS limit: ask for exactly what is needed
+  if (!raised && lds + sizeof(double) * (TB / 64) > LDS_DEFAULT) {
+    P3_TRY(raise_lds(k_tile_product<V, X, K>, (size_t)1024 * K * sizeof(double)));
+    raised = true;
   }
+  prod_task a{};
+  a.chunk_fix = L.chunk_fix.p;
+  a.ovf_ptr = L.ovf_ptr.p;
+  a.chunk_ovf = L.chunk_ovf.p;
+  a.ent_rc = L.ent_rc.p;
+  a.ent_v = ent_v;
+  a.dia = in_v;
+  a.w_in = L.w_in;
+  a.ntiles = L.ntiles;
+  a.lgT = L.lgT;
+  a.n = n;
+  a.shift = (double)shift;
+  a.x = x;
+  a.y = y;
+  a.z = ep.z;
+  a.beta = ep.beta;
+  a.partials = ep.partials;
+  a.done = ep.done;
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
-  k_tile_product<V, X, K><<<grid, TB, lds, s>>>(L.chunk_fix.p, L.ovf_ptr.p, L.chunk_ovf.p, L.ent_rc.p, ent_v, in_v,
-                                                L.w_in, L.ntiles, L.lgT, n, shift, x, y, ep);
+  k_tile_product<V, X, K><<<grid, TB, lds, s>>>(a);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;
@@ -328,6 +375,75 @@ pars3_status scatter_rows(const void *src, void *dst, const int32_t *idx, int64_
   else k_scatter<float><<<g, TB, 0, s>>>((const float *)src, (float *)dst, idx, n, k);
   P3_LAUNCHED();
   return PARS3_OK;
+}
+
+// ------------------------------------------------------------ batched products
+pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, prod_task *a, int *vkind) {
+  const layout &L = A->lay;
+  *a = prod_task{};
+  a->chunk_fix = L.chunk_fix.p;
+  a->ovf_ptr = L.ovf_ptr.p;
+  a->chunk_ovf = L.chunk_ovf.p;
+  a->ent_rc = L.ent_rc.p;
+  a->w_in = L.w_in;
+  a->ntiles = L.ntiles;
+  a->lgT = L.lgT;
+  a->n = (int32_t)A->n;
+  if (vec_dtype == PARS3_F64) {
+    if (!A->has_f64) return fail(PARS3_ESTATE, "batch: a matrix has no FP64 values");
+    a->ent_v = L.ent_f64.p;
+    a->dia = L.in_f64.p;
+    *vkind = PARS3_F64;
+    return PARS3_OK;
+  }
+  const bool use32 = A->has_f32 && value_dtype != PARS3_BF16;
+  const bool use16 = A->has_bf16 && value_dtype != PARS3_F32;
+  if (use32) {
+    a->ent_v = L.ent_f32.p;
+    a->dia = L.in_f32.p;
+    *vkind = PARS3_F32;
+  } else if (use16) {
+    a->ent_v = L.ent_bf16.p;
+    a->dia = L.in_bf16.p;
+    *vkind = PARS3_BF16;
+  } else {
+    return fail(PARS3_ESTATE, "batch: a matrix has no FP32 or BF16 values");
+  }
+  return PARS3_OK;
+}
+
+template <class V, class X, int K>
+static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, const int32_t *qbeg, int32_t *qctr,
+                                   int32_t grid, int32_t maxT, hipStream_t s) {
+  const size_t lds = (size_t)maxT * K * sizeof(double);
+  static bool raised = false;
+  if (!raised && lds + sizeof(double) * (TB / 64) + 64 > LDS_DEFAULT) {
+    P3_TRY(raise_lds(k_batch_product<V, X, K>, (size_t)1024 * K * sizeof(double)));
+    raised = true;
+  }
+  P3_TRY(fill_i32(qctr, 0, 8, s));
+  k_batch_product<V, X, K><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg, qctr);
+  P3_LAUNCHED();
+  return PARS3_OK;
+}
+
+template <class V, class X>
+static pars3_status launch_batch_v(int k, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
+                                   int32_t *qctr, int32_t grid, int32_t maxT, hipStream_t s) {
+  switch (k) {
+    case 1: return launch_batch_k<V, X, 1>(tasks, items, qbeg, qctr, grid, maxT, s);
+    case 2: return launch_batch_k<V, X, 2>(tasks, items, qbeg, qctr, grid, maxT, s);
+    case 4: return launch_batch_k<V, X, 4>(tasks, items, qbeg, qctr, grid, maxT, s);
+    case 8: return launch_batch_k<V, X, 8>(tasks, items, qbeg, qctr, grid, maxT, s);
+    default: return fail(PARS3_EINVAL, "batch: k must be 1, 2, 4 or 8 (got %d)", k);
+  }
+}
+
+pars3_status launch_batch(int vkind, int k, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
+                          int32_t *qctr, int32_t grid, int32_t maxT, hipStream_t s) {
+  if (vkind == PARS3_F64) return launch_batch_v<double, double>(k, tasks, items, qbeg, qctr, grid, maxT, s);
+  if (vkind == PARS3_F32) return launch_batch_v<float, float>(k, tasks, items, qbeg, qctr, grid, maxT, s);
+  return launch_batch_v<uint16_t, float>(k, tasks, items, qbeg, qctr, grid, maxT, s);
 }
 
 }  // namespace p3

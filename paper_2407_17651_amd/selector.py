@@ -36,6 +36,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DATA = os.path.join(HERE, "data", "selector_sweep_f32.npz")
+WEIGHTS = os.path.join(HERE, "data", "selector_mlp.npz")
 N_MATRICES = 2000
 N_HELD_OUT = 200
 FAMILIES = ("grid2d", "grid3d", "rgg2d", "chung_lu")
@@ -174,6 +175,30 @@ def regrets_all(times_us):
     return np.where(t > 0, t, np.inf) / best - 1.0
 
 
+def save_trained(mlp, path: str = WEIGHTS):
+    """Weights and scaler of a trained network (written by ``train-save``)."""
+    P = mlp.get_params()
+    mu, sd = mlp.get_scaler()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, sizes=np.array(mlp.sizes, np.int32), mean=mu, std=sd, **P)
+    return path
+
+
+def load_trained(p3, path: str = WEIGHTS, value_dtype=None):
+    """(network, default grid) restored from ``save_trained``'s file."""
+    with np.load(path) as z:
+        sizes = [int(v) for v in z["sizes"]]
+        P = {k: z[k] for k in p3.MLP.NAMES}
+        mu, sd = z["mean"], z["std"]
+    net = p3.MLP(*sizes, seed=0)
+    net.set_params(P)
+    net.set_scaler(mu, sd)
+    grid = p3.pars3_tune_grid_default(p3.F32 if value_dtype is None else value_dtype)
+    if len(grid) != sizes[3]:
+        raise ValueError("the saved network does not match the default grid")
+    return net, grid
+
+
 class TuneDB:
     """Tuning records keyed by a hash of the matrix structure (JSON file)."""
 
@@ -216,6 +241,10 @@ def main(argv=None):
     m = sub.add_parser("merge")
     m.add_argument("out")
     m.add_argument("inputs", nargs="+")
+    t = sub.add_parser("train-save")
+    t.add_argument("--data", default=DATA)
+    t.add_argument("--epochs", type=int, default=400)
+    t.add_argument("--out", default=WEIGHTS)
     e = sub.add_parser("evaluate")
     e.add_argument("--data", default=DATA)
     e.add_argument("--epochs", type=int, default=400)
@@ -230,6 +259,10 @@ def main(argv=None):
         print(f"[sweep] wrote {a.out}", flush=True)
     elif a.cmd == "merge":
         print(merge(a.inputs, a.out))
+    elif a.cmd == "train-save":
+        out, mlp = evaluate(load(a.data), epochs=a.epochs)
+        save_trained(mlp, a.out)
+        print(json.dumps(out), flush=True)
     else:
         out, _ = evaluate(load(a.data), epochs=a.epochs)
         print(json.dumps(out), flush=True)

@@ -1,0 +1,201 @@
+"""Batched products (one persistent graph-captured launch over many matrices,
+block right-hand sides) and batched MRS, against the oracle per matrix.
+
+Bars: as for single products (FP64 <= 1e-12, FP32 <= 1e-5 relative
+infinity-norm against the oracle on the same rounded values and vectors);
+every MRS solution has an oracle FP64 relative residual <= 1e-10."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2407_17651_amd as p3
+import synth
+from gpu_util import rel_inf, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_set(count, seed, n_lo=2000, n_hi=30000):
+    specs = synth.batch_specs(count, seed, n_lo, n_hi)
+    return specs, [synth.make(s, "uniform_f32") for s in specs]
+
+
+TILES = (64, 128, 256, 512, 1024)
+
+
+def reordered(Ls, value_dtype, keep=0, tiles=None):
+    mats = []
+    for i, L in enumerate(Ls):
+        T = TILES[i % len(TILES)] if tiles is None else tiles
+        mats.append(p3.Matrix(L).reorder(value_dtype=value_dtype, keep_fp64=keep, tile_rows=T,
+                                         w_in=(i % 3 == 0) * 2))
+    return mats
+
+
+def oracle_product(L, shift, X, vec):
+    B = oracle.permute(L, oracle.rcm(L))
+    Xr = X if vec == p3.F64 else X.astype(np.float32).astype(np.float64)
+    Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, "f64" if vec == p3.F64 else "f32")})
+    return oracle.spmv(Bv, shift, Xr)
+
+
+@pytest.mark.parametrize("k,value_dtype", [(8, p3.F32), (1, p3.F64), (4, p3.F64), (2, p3.BF16)])
+def test_batch_products_match_oracle(k, value_dtype):
+    specs, Ls = mixed_set(12, 77 + k)
+    print(f"[gpu] batch spmv k={k} dtype={value_dtype} sizes={[L.n for L in Ls]}", flush=True)
+    mats = reordered(Ls, value_dtype)
+    bat = p3.Batch(mats)
+    vec = p3.F64 if value_dtype == p3.F64 else p3.F32
+    tdt = torch.float64 if vec == p3.F64 else torch.float32
+    Xs = [synth.vector(L.n, 100 + i, k) if k > 1 else synth.vector(L.n, 100 + i) for i, L in enumerate(Ls)]
+    xs = [to_dev(X, tdt) for X in Xs]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    shifts = np.array([s["alpha"] for s in specs])
+    bat.spmv(xs, ys, shifts, k=k, vec_dtype=vec)
+    bat.spmv(xs, ys, shifts, k=k, vec_dtype=vec)  # graph replay
+    torch.cuda.synchronize()
+    tol = 1e-12 if vec == p3.F64 else 1e-5
+    if value_dtype == p3.BF16:
+        tol = 1e-5
+    for i, L in enumerate(Ls):
+        B = oracle.permute(L, oracle.rcm(L))
+        Xr = Xs[i] if vec == p3.F64 else Xs[i].astype(np.float32).astype(np.float64)
+        kind = {p3.F64: "f64", p3.F32: "f32", p3.BF16: "bf16"}[value_dtype]
+        Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, kind)})
+        want = oracle.spmv(Bv, shifts[i], Xr)
+        assert rel_inf(ys[i].cpu().numpy().astype(np.float64), want) <= tol, i
+
+
+def test_batch_recapture_on_new_pointers_and_shifts():
+    specs, Ls = mixed_set(6, 5)
+    mats = reordered(Ls, p3.F64)
+    bat = p3.Batch(mats)
+    xs = [to_dev(synth.vector(L.n, i)) for i, L in enumerate(Ls)]
+    y1 = [torch.empty_like(x) for x in xs]
+    y2 = [torch.empty_like(x) for x in xs]
+    bat.spmv(xs, y1, np.ones(6))
+    bat.spmv(xs, y2, np.full(6, -2.0))
+    bat.spmv(xs, y1, np.ones(6))
+    torch.cuda.synchronize()
+    for i, L in enumerate(Ls):
+        x = xs[i].cpu().numpy()
+        B = oracle.permute(L, oracle.rcm(L))
+        assert rel_inf(y1[i].cpu().numpy(), oracle.spmv(B, 1.0, x)) <= 1e-12
+        assert rel_inf(y2[i].cpu().numpy(), oracle.spmv(B, -2.0, x)) <= 1e-12
+
+
+def test_batch_queues_cover_every_item():
+    specs, Ls = mixed_set(20, 9)
+    mats = reordered(Ls, p3.F64)
+    bat = p3.Batch(mats)
+    info = bat.info()
+    q = info["queues"]
+    assert q[0] == 0 and q[8] == info["n_items"] and np.all(np.diff(q) >= 0)
+    assert info["n_items"] == sum(m.info()["n_tiles"] for m in mats)
+    assert info["grid"] % 8 == 0 and info["grid"] <= 2048
+
+
+def test_batch_with_empty_and_tiny_matrices():
+    Ls = [synth.grid2d(30, 1), synth.from_edges(1, [], seed=1), synth.from_edges(2, [(1, 0)], seed=2),
+          synth.rgg2d(3000, 8.0, 3)]
+    mats = [p3.Matrix(L).reorder() for L in Ls]
+    bat = p3.Batch(mats)
+    xs = [to_dev(synth.vector(L.n, 7 + i)) for i, L in enumerate(Ls)]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    bat.spmv(xs, ys, np.full(4, 0.25))
+    torch.cuda.synchronize()
+    for i, L in enumerate(Ls):
+        B = oracle.permute(L, oracle.rcm(L))
+        assert rel_inf(ys[i].cpu().numpy(), oracle.spmv(B, 0.25, xs[i].cpu().numpy())) <= 1e-12
+
+
+@pytest.mark.parametrize("order", [p3.ORDER_ORIGINAL, p3.ORDER_RCM])
+def test_batch_mrs_converges_per_system(order):
+    specs, Ls = mixed_set(10, 31, 2000, 20000)
+    alphas = np.array([s["alpha"] for s in specs])
+    print(f"[gpu] batch mrs order={order} alphas={alphas.round(2).tolist()}", flush=True)
+    mats = reordered(Ls, p3.F32, keep=1)
+    bat = p3.Batch(mats)
+    bs, xs, bh = [], [], []
+    for i, L in enumerate(Ls):
+        b = oracle.spmv(L, alphas[i], np.ones(L.n))
+        if order == p3.ORDER_RCM:
+            b = b[oracle.rcm(L)]
+        bh.append(b)
+        bs.append(to_dev(b))
+        xs.append(torch.zeros(L.n, dtype=torch.float64, device="cuda"))
+    st, infos = bat.mrs(alphas, bs, xs, order=order, tol=1e-10, maxit=5000)
+    torch.cuda.synchronize()
+    assert st == p3.OK, infos
+    for i, L in enumerate(Ls):
+        x = xs[i].cpu().numpy()
+        if order == p3.ORDER_RCM:
+            perm = oracle.rcm(L)
+            xo = np.empty_like(x)
+            xo[perm] = x
+            b = np.empty_like(bh[i])
+            b[perm] = bh[i]
+        else:
+            xo, b = x, bh[i]
+        res = oracle.residual(L, alphas[i], b, xo)
+        assert res <= 1e-10, (i, res, infos[i])
+        assert abs(res - infos[i]["relres"]) <= 1e-3 * res + 1e-15
+        _, io, _ = oracle.mrs(L, alphas[i], b, tol=1e-10, maxit=5000)
+        assert abs(infos[i]["iters"] - io["iters"]) <= 2 + io["iters"] // 100, (i, infos[i]["iters"], io["iters"])
+
+
+def test_batch_mrs_matches_single_solves():
+    specs, Ls = mixed_set(5, 41, 3000, 8000)
+    alphas = np.array([s["alpha"] for s in specs])
+    mats = reordered(Ls, p3.F64, tiles=256)
+    bat = p3.Batch(mats)
+    bs = [to_dev(oracle.spmv(L, alphas[i], synth.vector(L.n, i))) for i, L in enumerate(Ls)]
+    xs = [torch.zeros(L.n, dtype=torch.float64, device="cuda") for L in Ls]
+    st, infos = bat.mrs(alphas, bs, xs, order=p3.ORDER_ORIGINAL, tol=1e-11, maxit=3000)
+    assert st == p3.OK
+    for i, M in enumerate(mats):
+        x1 = torch.zeros_like(xs[i])
+        st1, info1, _ = M.mrs(alphas[i], bs[i], x1, order=p3.ORDER_ORIGINAL, tol=1e-11, maxit=3000)
+        assert abs(info1["iters"] - infos[i]["iters"]) <= 1
+        assert rel_inf(xs[i].cpu().numpy(), x1.cpu().numpy()) <= 1e-9
+
+
+def test_batch_errors():
+    L = synth.grid2d(10, 1)
+    with pytest.raises(p3.Pars3Error) as e:
+        p3.Batch([p3.Matrix(L)])
+    assert e.value.status == p3.ESTATE
+    bat = p3.Batch([p3.Matrix(L).reorder()])
+    b = to_dev(np.ones(L.n))
+    x = to_dev(np.zeros(L.n))
+    with pytest.raises(p3.Pars3Error) as e:
+        bat.mrs([1.0], [b], [x], precision=p3.F32)
+    assert e.value.status == p3.EINVAL
+    with pytest.raises(p3.Pars3Error) as e:
+        bat.spmv([x], [b], k=3)
+    assert e.value.status == p3.EINVAL
+    with pytest.raises(p3.Pars3Error) as e:
+        bat.spmv([x], [b], vec_dtype=p3.F32)  # FP64 values only
+    assert e.value.status == p3.ESTATE
+
+
+def test_batched_workload_full_size_sampled():
+    """The 256-matrix workload (n log-uniform in [2k, 200k]), k = 8 FP32
+    right-hand sides, one launch; every 16th matrix checked against the
+    oracle, every matrix checked for finite output."""
+    specs = synth.batch_specs(256)
+    Ls = [synth.make(s, "uniform_f32") for s in specs]
+    print(f"[gpu] batch full size sum_n={sum(L.n for L in Ls)} sum_nnz={sum(L.nnz for L in Ls)}", flush=True)
+    mats = [p3.Matrix(L).reorder(value_dtype=p3.F32) for L in Ls]
+    bat = p3.Batch(mats)
+    Xs = [synth.vector(L.n, 500 + i, 8).astype(np.float32) for i, L in enumerate(Ls)]
+    xs = [to_dev(X, torch.float32) for X in Xs]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    shifts = np.array([s["alpha"] for s in specs])
+    bat.spmv(xs, ys, shifts, k=8, vec_dtype=p3.F32)
+    torch.cuda.synchronize()
+    for i in range(0, 256, 16):
+        want = oracle_product(Ls[i], shifts[i], Xs[i].astype(np.float64), p3.F32)
+        assert rel_inf(ys[i].cpu().numpy().astype(np.float64), want) <= 1e-5, i
+    assert all(bool(torch.isfinite(y).all()) for y in ys)
