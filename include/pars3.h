@@ -124,7 +124,9 @@ pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *p, void *s
  * stored values are FP64 and PARS3_F32 when they are FP32 or BF16 (products
  * formed in FP32, summed per row in FP64, results rounded to FP32).  order = PARS3_ORDER_RCM: x and y are in the reordered
  * numbering; PARS3_ORDER_ORIGINAL: in the caller's numbering (a gather and a
- * scatter are added).  x and y must not overlap.  Asynchronous.  Errors:
+ * scatter are added).  x and y must not overlap and, when k > 1, must be
+ * 16-byte aligned (rows are read and written as 16-byte vectors).
+ * Asynchronous.  Errors:
  * ESTATE before pars3_reorder or for a dtype mismatch; EINVAL otherwise. */
 pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x, void *y, int32_t k, int32_t vec_dtype,
                         int32_t order, void *stream);
@@ -274,7 +276,8 @@ pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, dou
  * and split with its own configuration, processed together: one persistent
  * launch per product walks a work list of (matrix, tile) items split into 8
  * per-XCD queues of equal estimated cost (matrices largest first, tiles
- * ascending); each launch is captured in a hipGraph and replayed.
+ * ascending), each queue taken round-robin by the persistent workgroups of
+ * its XCD; each launch is captured in a hipGraph and replayed.
  *  pars3_batch_create: m reordered handles (the batch keeps pointers to them;
  *    they must outlive it and must not be re-split while it exists).
  *  pars3_batch_info: number of items, persistent grid size and the 9 queue
@@ -282,7 +285,8 @@ pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, dou
  *  pars3_batch_spmv: y_i = shifts[i] x_i + S_i x_i for every matrix i, with
  *    host arrays x[m], y[m] of device pointers (n_i x k row-major vectors in
  *    matrix i's reordered numbering, k in {1, 2, 4, 8}); shifts (host, m) may
- *    be NULL (all zero); vec_dtype and value_dtype as in pars3_spmv (every
+ *    be NULL (all zero); 16-byte aligned when k > 1; vec_dtype and
+ *    value_dtype as in pars3_spmv (every
  *    matrix must store the values used).  The launch is captured once per
  *    distinct (pointers, shifts, k, dtype) and replayed while they repeat.
  *    Asynchronous on `stream`.

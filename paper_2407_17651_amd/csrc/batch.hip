@@ -6,12 +6,11 @@
 // (the tile's share of the matrix's stored entries plus its rows).  Matrices
 // are taken largest first and their tiles in ascending order (so the two
 // reads of a tile-pair block stay close in time); the sequence is cut into 8
-// contiguous queues of equal cost, one per XCD.  A persistent workgroup of
-// XCD q takes the next item of queue q with one atomic until the queue is
-// empty (see k_batch_product).
+// contiguous queues of equal cost, one per XCD; the persistent workgroups of
+// XCD q take the items of queue q round-robin (see k_batch_product).
 //
-// The launch of a product (counter reset + persistent kernel) is captured
-// once per set of vector pointers in a hipGraph and replayed.
+// The launch of a product is captured once per set of vector pointers in a
+// hipGraph and replayed.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -279,8 +278,11 @@ extern "C" pars3_status pars3_batch_spmv(pars3_batch *B, const double *shifts, c
   if (k != 1 && k != 2 && k != 4 && k != 8) return fail(PARS3_EINVAL, "batch spmv: k must be 1, 2, 4 or 8");
   if (vec_dtype != PARS3_F64 && vec_dtype != PARS3_F32) return fail(PARS3_EINVAL, "batch spmv: bad vec_dtype");
   const int32_t m = (int32_t)B->mats.size();
-  for (int32_t i = 0; i < m; i++)
+  for (int32_t i = 0; i < m; i++) {
     if (B->mats[i]->n > 0 && (!x[i] || !y[i])) return fail(PARS3_EINVAL, "batch spmv: NULL vector of matrix %d", i);
+    if (k > 1 && (((uintptr_t)x[i] | (uintptr_t)y[i]) & 15u))
+      return fail(PARS3_EINVAL, "batch spmv: vectors of matrix %d must be 16-byte aligned when k > 1", i);
+  }
   std::vector<prod_task> t;
   int vk = -1;
   P3_TRY(batch_tasks(B, shifts, x, y, vec_dtype, value_dtype, t, &vk));

@@ -148,6 +148,8 @@ extern "C" pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x,
   if (k != 1 && k != 2 && k != 4 && k != 8) return fail(PARS3_EINVAL, "spmv: k must be 1, 2, 4 or 8");
   if (vec_dtype != PARS3_F64 && vec_dtype != PARS3_F32) return fail(PARS3_EINVAL, "spmv: bad vec_dtype");
   if (order != PARS3_ORDER_RCM && order != PARS3_ORDER_ORIGINAL) return fail(PARS3_EINVAL, "spmv: bad order");
+  if (k > 1 && (((uintptr_t)x | (uintptr_t)y) & 15u))
+    return fail(PARS3_EINVAL, "spmv: x and y must be 16-byte aligned when k > 1");
   if (A->n == 0) return PARS3_OK;
   if (!x || !y) return fail(PARS3_EINVAL, "spmv: NULL vector");
   const size_t elem = vec_dtype == PARS3_F64 ? 8 : 4;

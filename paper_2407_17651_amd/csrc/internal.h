@@ -321,7 +321,7 @@ struct prod_task {
 // whichever is stored); *vkind receives the value type used.
 pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, prod_task *a, int *vkind);
 // Persistent product over many tasks: items (task, tile) in 8 queues
-// [qbeg[q], qbeg[q+1]), counters qctr[8] (cleared here by a fill kernel).
+// [qbeg[q], qbeg[q+1]), one per XCD, taken round-robin (qctr is unused).
 // maxT: the largest tile height among the tasks.
 pars3_status launch_batch(int vkind, int k, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
                           int32_t *qctr, int32_t grid, int32_t maxT, hipStream_t s);

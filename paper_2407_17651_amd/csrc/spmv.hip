@@ -21,6 +21,7 @@
 // otherwise; products are formed in the vector precision and summed in FP64
 // in LDS.  k right-hand sides are stored row-major.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -29,6 +30,10 @@ namespace p3 {
 static constexpr int TB = 256;
 static constexpr size_t LDS_DEFAULT = 64 * 1024;  // dynamic LDS available without an attribute
 static constexpr int PRE = CHUNKS_FIXED / (TB / 64);  // chunks per wavefront whose loads are issued together
+// LDS row stride of the FP64 row sums: K + 1 words for several right-hand
+// sides, so that the K sums of rows with equal residues do not share banks
+template <int K>
+constexpr int KP = K == 1 ? 1 : K + 1;
 
 template <class V>
 struct vload;
@@ -48,6 +53,48 @@ struct vload<uint16_t> {
     return __uint_as_float((uint32_t)__builtin_nontemporal_load(p + i) << 16);
   }
   static __device__ __forceinline__ float ld(const uint16_t *p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
+};
+
+// The k values of one row of x (or y) as 16-byte vector accesses where the
+// row is a whole number of them (rows of k >= 2 values are 16-byte aligned:
+// the library requires 16-byte aligned vectors when k >= 2).
+template <class X, int K>
+struct rowvec {
+  static constexpr int W = 16 / sizeof(X);  // values per 16 bytes
+  static constexpr bool VEC = K >= W && K % W == 0;
+  static __device__ __forceinline__ void load(const X *__restrict__ p, int64_t row, X (&v)[K]) {
+    if constexpr (VEC) {
+      using V4 = typename std::conditional<sizeof(X) == 8, double2, float4>::type;
+      const V4 *q = reinterpret_cast<const V4 *>(p + row * K);
+#pragma unroll
+      for (int u = 0; u < K / W; u++) {
+        const V4 t = q[u];
+        const X *tt = reinterpret_cast<const X *>(&t);
+#pragma unroll
+        for (int w = 0; w < W; w++) v[u * W + w] = tt[w];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < K; c++) v[c] = p[row * K + c];
+    }
+  }
+  static __device__ __forceinline__ void store(X *__restrict__ p, int64_t row, const X (&v)[K]) {
+    if constexpr (VEC) {
+      using V4 = typename std::conditional<sizeof(X) == 8, double2, float4>::type;
+      V4 *q = reinterpret_cast<V4 *>(p + row * K);
+#pragma unroll
+      for (int u = 0; u < K / W; u++) {
+        V4 t;
+        X *tt = reinterpret_cast<X *>(&t);
+#pragma unroll
+        for (int w = 0; w < W; w++) tt[w] = v[u * W + w];
+        q[u] = t;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < K; c++) p[row * K + c] = v[c];
+    }
+  }
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs: block b runs on XCD
@@ -95,14 +142,19 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
     }
   }
 #pragma unroll
-  for (int q = 0; q < PRE; q++)
+  for (int q = 0; q < PRE; q++) {
+    if (slot[q] >= 0) {
+      rowvec<X, K>::load(x, xrow[q], xv[q]);
+    } else {
 #pragma unroll
-    for (int c = 0; c < K; c++) xv[q][c] = slot[q] >= 0 ? x[(int64_t)xrow[q] * K + c] : (X)0;
+      for (int c = 0; c < K; c++) xv[q][c] = (X)0;
+    }
+  }
 #pragma unroll
   for (int q = 0; q < PRE; q++)
     if (slot[q] >= 0) {
 #pragma unroll
-      for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * K + c], (double)(coef[q] * xv[q][c]));
+      for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * KP<K> + c], (double)(coef[q] * xv[q][c]));
     }
 }
 
@@ -136,9 +188,13 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   for (int q = 0; q < PRE; q++) d[q] = a.chunk_fix[(int64_t)t * CHUNKS_FIXED + wave + q * (TB / 64)];
   const int32_t o0 = a.ovf_ptr[t], o1 = a.ovf_ptr[t + 1];
   X xown[K];
+  if ((int32_t)threadIdx.x < rows) {
+    rowvec<X, K>::load(x, (int64_t)r0 + threadIdx.x, xown);
+  } else {
 #pragma unroll
-  for (int c = 0; c < K; c++) xown[c] = (int32_t)threadIdx.x < rows ? x[((int64_t)r0 + threadIdx.x) * K + c] : (X)0;
-  for (int32_t s = threadIdx.x; s < rows * K; s += TB) ys[s] = 0.0;
+    for (int c = 0; c < K; c++) xown[c] = (X)0;
+  }
+  for (int32_t s = threadIdx.x; s < rows * KP<K>; s += TB) ys[s] = 0.0;
   __syncthreads();
   chunk_group<V, X, K>(d, lane, lgT, a.ent_rc, ent_v, x, ys);
   for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
@@ -156,7 +212,7 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
     X acc[K];
 #pragma unroll
     for (int c = 0; c < K; c++)
-      acc[c] = shift * (r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c]) + (X)ys[r * K + c];
+      acc[c] = shift * (r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c]) + (X)ys[r * KP<K> + c];
     for (int32_t k = 1; k <= w_in; k++) {
       const int64_t bse = (int64_t)(k - 1) * n;
       if (i - k >= 0) {
@@ -179,11 +235,9 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
 #pragma unroll
       for (int c = 0; c < K; c++) acc[c] += zb * z[i * K + c];
     }
+    rowvec<X, K>::store(y, i, acc);
 #pragma unroll
-    for (int c = 0; c < K; c++) {
-      y[i * K + c] = acc[c];
-      sq += (double)acc[c] * (double)acc[c];
-    }
+    for (int c = 0; c < K; c++) sq += (double)acc[c] * (double)acc[c];
   }
   if (a.partials) {
     // partial sum of squares of the tile's outputs, in a fixed order
@@ -210,25 +264,22 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   tile_body<V, X, K>(a, t, ys, s_red);
 }
 
-// Many matrices in one launch: persistent workgroups take (matrix, tile)
-// items from the queue of their XCD (workgroup b runs on XCD b % 8) with one
-// atomic per item, until the queue is empty; no workgroup waits for another.
+// Many matrices in one launch: the (matrix, tile) items are split into 8
+// queues, one per XCD (workgroup b runs on XCD b % 8).  The J = grid / 8
+// persistent workgroups of an XCD take the items of its queue round-robin
+// (workgroup j: items j, j + J, j + 2J, ...); the queues are ordered by cost,
+// so neighbouring items cost about the same and no counter is shared.
 // Items of a matrix whose solver has finished are skipped.
 template <class V, class X, int K>
 __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restrict__ tasks,
                                                       const int2 *__restrict__ items,
-                                                      const int32_t *__restrict__ qbeg, int32_t *__restrict__ qctr) {
+                                                      const int32_t *__restrict__ qbeg) {
   __shared__ double s_red[TB / 64];
-  __shared__ int32_t s_item;
   extern __shared__ double ys[];
   const int q = blockIdx.x & 7;
+  const int32_t J = gridDim.x >> 3, j = blockIdx.x >> 3;
   const int32_t end = qbeg[q + 1];
-  for (;;) {
-    if (threadIdx.x == 0) s_item = qbeg[q] + atomicAdd(&qctr[q], 1);
-    __syncthreads();
-    const int32_t it = s_item;
-    __syncthreads();  // every thread has read s_item before it is replaced
-    if (it >= end) break;
+  for (int32_t it = qbeg[q] + j; it < end; it += J) {
     const int2 w = items[it];
     const prod_task &a = tasks[w.x];
     if (a.done && *a.done) continue;
@@ -250,10 +301,10 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   const layout &L = A->lay;
   const int32_t n = (int32_t)A->n;
   if (n == 0) return PARS3_OK;
-  const size_t lds = (size_t)L.T * K * sizeof(double);
+  const size_t lds = (size_t)L.T * KP<K> * sizeof(double);
   static bool raised = false;  // above the default dynamic LDS limit: ask for exactly what is needed
   if (!raised && lds + sizeof(double) * (TB / 64) > LDS_DEFAULT) {
-    P3_TRY(raise_lds(k_tile_product<V, X, K>, (size_t)1024 * K * sizeof(double)));
+    P3_TRY(raise_lds(k_tile_product<V, X, K>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
   prod_task a{};
@@ -415,14 +466,14 @@ pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, pr
 template <class V, class X, int K>
 static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, const int32_t *qbeg, int32_t *qctr,
                                    int32_t grid, int32_t maxT, hipStream_t s) {
-  const size_t lds = (size_t)maxT * K * sizeof(double);
+  const size_t lds = (size_t)maxT * KP<K> * sizeof(double);
   static bool raised = false;
   if (!raised && lds + sizeof(double) * (TB / 64) + 64 > LDS_DEFAULT) {
-    P3_TRY(raise_lds(k_batch_product<V, X, K>, (size_t)1024 * K * sizeof(double)));
+    P3_TRY(raise_lds(k_batch_product<V, X, K>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
-  P3_TRY(fill_i32(qctr, 0, 8, s));
-  k_batch_product<V, X, K><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg, qctr);
+  (void)qctr;
+  k_batch_product<V, X, K><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
   P3_LAUNCHED();
   return PARS3_OK;
 }

@@ -103,6 +103,17 @@ def test_block_right_hand_sides_tile_sizes(tile_rows, k):
     assert rel_inf(got, oracle.spmv(B, -0.5, X)) <= 1e-12
 
 
+def test_misaligned_block_vectors_rejected():
+    L = synth.grid2d(20, 1)
+    M = p3.Matrix(L).reorder()
+    buf = torch.zeros(2 * L.n + 1, dtype=torch.float64, device="cuda")
+    y = torch.zeros(2 * L.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(p3.Pars3Error) as e:
+        p3.pars3_spmv(M.h, 0.0, buf[1:], y, 2, p3.F64, p3.ORDER_RCM)
+    assert e.value.status == p3.EINVAL
+    p3.pars3_spmv(M.h, 0.0, buf[1:1 + L.n], y[:L.n], 1, p3.F64, p3.ORDER_RCM)  # k = 1: any alignment
+
+
 def test_original_order():
     L = synth.rgg2d(10000, 10.0, 14)
     M = p3.Matrix(L).reorder()
