@@ -27,7 +27,7 @@ struct pars3_batch {
   std::vector<int32_t> poff;   // partial-sum offsets (prefix of tiles)
   int32_t maxT = 64, grid = 0, nitems = 0;
   p3::dbuf<int2> items;
-  p3::dbuf<int32_t> qbeg, qctr;
+  p3::dbuf<int32_t> qbeg;
   hipStream_t gs = nullptr;  // capture stream
   // product graph cache (one pointer set)
   p3::dbuf<p3::prod_task> tasks;
@@ -221,8 +221,7 @@ extern "C" pars3_status pars3_batch_create(int32_t m, pars3_matrix *const *mats,
   B->nitems = (int32_t)it.size();
   // persistent grid: up to 8 workgroups per CU over 256 CUs, a multiple of 8
   B->grid = (int32_t)std::min<int64_t>(2048, 8 * cdiv(std::max<int64_t>(B->nitems, 1), 8));
-  if (B->items.alloc(std::max<size_t>(it.size(), 1)) != hipSuccess || B->qbeg.alloc(9) != hipSuccess ||
-      B->qctr.alloc(8) != hipSuccess || B->tasks.alloc(m) != hipSuccess) {
+  if (B->items.alloc(std::max<size_t>(it.size(), 1)) != hipSuccess || B->qbeg.alloc(9) != hipSuccess || B->tasks.alloc(m) != hipSuccess) {
     (void)hipGetLastError();
     return bad(fail(PARS3_ENOMEM, "batch: device allocation failed"));
   }
@@ -296,7 +295,7 @@ extern "C" pars3_status pars3_batch_spmv(pars3_batch *B, const double *shifts, c
     P3_HIP(hipStreamSynchronize(s));
     P3_HIP(hipMemcpy(B->tasks.p, t.data(), m * sizeof(prod_task), hipMemcpyHostToDevice));
     P3_HIP(hipStreamBeginCapture(B->gs, hipStreamCaptureModeThreadLocal));
-    pars3_status st = launch_batch(vk, k, B->tasks.p, B->items.p, B->qbeg.p, B->qctr.p, B->grid, B->maxT, B->gs);
+    pars3_status st = launch_batch(vk, k, false, B->tasks.p, B->items.p, B->qbeg.p, B->grid, B->maxT, B->gs);
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(B->gs, &g);
     if (st != PARS3_OK) {
@@ -429,7 +428,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   k_bmrs_const<<<g1(m), BT, 0, s>>>(dev.p, m);
   k_bnorm<<<m, BT, 0, s>>>(Bv.p, doff.p, nb2.p);
   P3_LAUNCHED();
-  P3_TRY(launch_batch(PARS3_F64, 1, tk.p, B->items.p, B->qbeg.p, B->qctr.p, B->grid, B->maxT, s));
+  P3_TRY(launch_batch(PARS3_F64, 1, true, tk.p, B->items.p, B->qbeg.p, B->grid, B->maxT, s));
   k_bnorm<<<m, BT, 0, s>>>(Y.p, doff.p, nr2.p);
   k_bmrs_init<<<g1(m), BT, 0, s>>>(P, nb2.p, nr2.p, alph.p, o.tol, o.maxit, m);
   if (nvb) k_bmrs_start<<<nvb, BT, 0, s>>>(P);
@@ -440,8 +439,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   pars3_status st = PARS3_OK;
   P3_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   for (int par = 0; par < 2 && st == PARS3_OK; par++) {
-    st = launch_batch(PARS3_F64, 1, tk.p + (size_t)(1 + par) * m, B->items.p, B->qbeg.p, B->qctr.p, B->grid, B->maxT,
-                      s);
+    st = launch_batch(PARS3_F64, 1, true, tk.p + (size_t)(1 + par) * m, B->items.p, B->qbeg.p, B->grid, B->maxT, s);
     if (st != PARS3_OK) break;
     k_bmrs_scalar<<<m, 1024, 0, s>>>(P, par, nullptr);
     if (nvb) k_bmrs_vec<<<nvb, BT, 0, s>>>(P, par);
@@ -473,7 +471,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
     return st;
   }
   // true residuals and outputs
-  P3_TRY(launch_batch(PARS3_F64, 1, tk.p, B->items.p, B->qbeg.p, B->qctr.p, B->grid, B->maxT, s));
+  P3_TRY(launch_batch(PARS3_F64, 1, true, tk.p, B->items.p, B->qbeg.p, B->grid, B->maxT, s));
   k_bnorm<<<m, BT, 0, s>>>(Y.p, doff.p, nr2.p);
   P3_LAUNCHED();
   std::vector<double> hr(m), hb(m);

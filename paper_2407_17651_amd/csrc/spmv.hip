@@ -166,8 +166,9 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
 // of descriptors sits at fixed positions per tile, so its loads depend on
 // nothing.  Partial sums are kept in FP64 in LDS whatever the vector type
 // (products are formed in the vector precision); LDS adds of FP64 measured
-// faster than of FP32 here.  Called by every thread of the workgroup.
-template <class V, class X, int K>
+// faster than of FP32 here.  Called by every thread of the workgroup.  EP:
+// the solver epilogue (y += beta z, per-tile sums of y^2) is compiled in.
+template <class V, class X, int K, bool EP>
 __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double *ys, double *s_red) {
   const V *__restrict__ ent_v = (const V *)a.ent_v;
   const V *__restrict__ dia = (const V *)a.dia;
@@ -230,7 +231,7 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
         }
       }
     }
-    if (z) {
+    if (EP && z) {
       const X zb = (X)*a.beta;
 #pragma unroll
       for (int c = 0; c < K; c++) acc[c] += zb * z[i * K + c];
@@ -239,7 +240,7 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
 #pragma unroll
     for (int c = 0; c < K; c++) sq += (double)acc[c] * (double)acc[c];
   }
-  if (a.partials) {
+  if (EP && a.partials) {
     // partial sum of squares of the tile's outputs, in a fixed order
 #pragma unroll
     for (int d2 = 32; d2 >= 1; d2 >>= 1) sq += __shfl_xor(sq, d2, 64);
@@ -253,15 +254,16 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   }
 }
 
-// One matrix: one workgroup per tile.
-template <class V, class X, int K>
+// One matrix: one workgroup per tile.  EP: with the solver epilogue (a
+// finished solver's done flag skips the whole launch).
+template <class V, class X, int K, bool EP>
 __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   __shared__ double s_red[TB / 64];
   extern __shared__ double ys[];
-  if (a.done && *a.done) return;  // a solver that has finished skips its remaining products
+  if (EP && a.done && *a.done) return;
   const int32_t t = xcd_tile(blockIdx.x, a.ntiles);
   if (t >= a.ntiles) return;
-  tile_body<V, X, K>(a, t, ys, s_red);
+  tile_body<V, X, K, EP>(a, t, ys, s_red);
 }
 
 // Many matrices in one launch: the (matrix, tile) items are split into 8
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
 // (workgroup j: items j, j + J, j + 2J, ...); the queues are ordered by cost,
 // so neighbouring items cost about the same and no counter is shared.
 // Items of a matrix whose solver has finished are skipped.
-template <class V, class X, int K>
+template <class V, class X, int K, bool EP>
 __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restrict__ tasks,
                                                       const int2 *__restrict__ items,
                                                       const int32_t *__restrict__ qbeg) {
@@ -282,8 +284,8 @@ __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restric
   for (int32_t it = qbeg[q] + j; it < end; it += J) {
     const int2 w = items[it];
     const prod_task &a = tasks[w.x];
-    if (a.done && *a.done) continue;
-    tile_body<V, X, K>(a, w.y, ys, s_red);
+    if (EP && a.done && *a.done) continue;
+    tile_body<V, X, K, EP>(a, w.y, ys, s_red);
     __syncthreads();  // ys and s_red are reused by the next item
   }
 }
@@ -295,7 +297,7 @@ static pars3_status raise_lds(F *kernel, size_t lds) {
   return PARS3_OK;
 }
 
-template <class V, class X, int K>
+template <class V, class X, int K, bool EP>
 static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shift, const X *x, X *y, hipStream_t s,
                            const epilogue<X> &ep) {
   const layout &L = A->lay;
@@ -304,7 +306,7 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   const size_t lds = (size_t)L.T * KP<K> * sizeof(double);
   static bool raised = false;  // above the default dynamic LDS limit: ask for exactly what is needed
   if (!raised && lds + sizeof(double) * (TB / 64) > LDS_DEFAULT) {
-    P3_TRY(raise_lds(k_tile_product<V, X, K>, (size_t)1024 * KP<K> * sizeof(double)));
+    P3_TRY(raise_lds(k_tile_product<V, X, K, EP>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
   prod_task a{};
@@ -327,7 +329,7 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   a.done = ep.done;
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
-  k_tile_product<V, X, K><<<grid, TB, lds, s>>>(a);
+  k_tile_product<V, X, K, EP><<<grid, TB, lds, s>>>(a);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;
@@ -339,12 +341,17 @@ static pars3_status dispatch_k(pars3_matrix *A, const V *in_v, const V *ent_v, d
   const X *xx = (const X *)x;
   X *yy = (X *)y;
   epilogue<X> ep{};
-  if (epv) ep = *(const epilogue<X> *)epv;
+  if (epv) {
+    // products with the solver epilogue are a kernel of their own
+    ep = *(const epilogue<X> *)epv;
+    if (k != 1) return fail(PARS3_EINVAL, "spmv: the solver epilogue takes one right-hand side");
+    return launch<V, X, 1, true>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+  }
   switch (k) {
-    case 1: return launch<V, X, 1>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
-    case 2: return launch<V, X, 2>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
-    case 4: return launch<V, X, 4>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
-    case 8: return launch<V, X, 8>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 1: return launch<V, X, 1, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 2: return launch<V, X, 2, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 4: return launch<V, X, 4, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 8: return launch<V, X, 8, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
     default: return fail(PARS3_EINVAL, "spmv: k must be 1, 2, 4 or 8 (got %d)", k);
   }
 }
@@ -463,38 +470,41 @@ pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, pr
   return PARS3_OK;
 }
 
-template <class V, class X, int K>
-static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, const int32_t *qbeg, int32_t *qctr,
-                                   int32_t grid, int32_t maxT, hipStream_t s) {
+template <class V, class X, int K, bool EP>
+static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, const int32_t *qbeg, int32_t grid,
+                                   int32_t maxT, hipStream_t s) {
   const size_t lds = (size_t)maxT * KP<K> * sizeof(double);
   static bool raised = false;
   if (!raised && lds + sizeof(double) * (TB / 64) + 64 > LDS_DEFAULT) {
-    P3_TRY(raise_lds(k_batch_product<V, X, K>, (size_t)1024 * KP<K> * sizeof(double)));
+    P3_TRY(raise_lds(k_batch_product<V, X, K, EP>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
-  (void)qctr;
-  k_batch_product<V, X, K><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
+  k_batch_product<V, X, K, EP><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
   P3_LAUNCHED();
   return PARS3_OK;
 }
 
 template <class V, class X>
-static pars3_status launch_batch_v(int k, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
-                                   int32_t *qctr, int32_t grid, int32_t maxT, hipStream_t s) {
+static pars3_status launch_batch_v(int k, bool ep, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
+                                   int32_t grid, int32_t maxT, hipStream_t s) {
+  if (ep) {
+    if (k != 1) return fail(PARS3_EINVAL, "batch: the solver epilogue takes one right-hand side");
+    return launch_batch_k<V, X, 1, true>(tasks, items, qbeg, grid, maxT, s);
+  }
   switch (k) {
-    case 1: return launch_batch_k<V, X, 1>(tasks, items, qbeg, qctr, grid, maxT, s);
-    case 2: return launch_batch_k<V, X, 2>(tasks, items, qbeg, qctr, grid, maxT, s);
-    case 4: return launch_batch_k<V, X, 4>(tasks, items, qbeg, qctr, grid, maxT, s);
-    case 8: return launch_batch_k<V, X, 8>(tasks, items, qbeg, qctr, grid, maxT, s);
+    case 1: return launch_batch_k<V, X, 1, false>(tasks, items, qbeg, grid, maxT, s);
+    case 2: return launch_batch_k<V, X, 2, false>(tasks, items, qbeg, grid, maxT, s);
+    case 4: return launch_batch_k<V, X, 4, false>(tasks, items, qbeg, grid, maxT, s);
+    case 8: return launch_batch_k<V, X, 8, false>(tasks, items, qbeg, grid, maxT, s);
     default: return fail(PARS3_EINVAL, "batch: k must be 1, 2, 4 or 8 (got %d)", k);
   }
 }
 
-pars3_status launch_batch(int vkind, int k, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
-                          int32_t *qctr, int32_t grid, int32_t maxT, hipStream_t s) {
-  if (vkind == PARS3_F64) return launch_batch_v<double, double>(k, tasks, items, qbeg, qctr, grid, maxT, s);
-  if (vkind == PARS3_F32) return launch_batch_v<float, float>(k, tasks, items, qbeg, qctr, grid, maxT, s);
-  return launch_batch_v<uint16_t, float>(k, tasks, items, qbeg, qctr, grid, maxT, s);
+pars3_status launch_batch(int vkind, int k, bool ep, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
+                          int32_t grid, int32_t maxT, hipStream_t s) {
+  if (vkind == PARS3_F64) return launch_batch_v<double, double>(k, ep, tasks, items, qbeg, grid, maxT, s);
+  if (vkind == PARS3_F32) return launch_batch_v<float, float>(k, ep, tasks, items, qbeg, grid, maxT, s);
+  return launch_batch_v<uint16_t, float>(k, ep, tasks, items, qbeg, grid, maxT, s);
 }
 
 }  // namespace p3
