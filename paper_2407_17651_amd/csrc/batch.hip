@@ -89,7 +89,8 @@ __global__ void k_bmrs_init(bmrs_ptrs p, const double *__restrict__ bn2, const d
   d.c1[0] = 1.0;
   d.c2[0] = 1.0;
   d.eta[0] = beta1;
-  d.delta = d.eps = d.gamma = d.ceta = d.inv_beta = 0.0;
+  d.delta = d.eps = d.gamma = d.ceta = d.inv_beta = d.vnrm_inv = d.scaleS = d.zcoef = 0.0;
+  d.nrm[0] = d.nrm[1] = 1.0;
   d.bnorm = bnorm > 0.0 ? bnorm : 1.0;
   d.tol_abs = tol * bnorm;
   d.alpha = alpha[i];

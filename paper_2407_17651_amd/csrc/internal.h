@@ -239,12 +239,27 @@ struct epilogue {
   const double *beta = nullptr;
   double *partials = nullptr;
   const int32_t *done = nullptr;
+  // fused MRS iteration (one right-hand side): y = (*scale) (S x) + (*beta) z,
+  // and, while *active, the previous iteration's vector update on the
+  // tile's rows: p = (z vec[4] - vec[0] p1 - vec[1] p2) / vec[2] written over
+  // p2, xs += vec[3] p
+  const double *scale = nullptr;
+  const double *vec = nullptr;
+  const int32_t *active = nullptr;
+  const X *p1 = nullptr;
+  X *p2 = nullptr;
+  X *xs = nullptr;
 };
 // Device state of one MRS run.  Rotation state is double-buffered by
 // iteration parity: iteration j reads slot j&1 and writes slot (j+1)&1.
 struct mrs_dev {
   double beta[2], c1[2], s1[2], c2[2], s2[2], eta[2];
-  double delta, eps, gamma, ceta, inv_beta;  // this iteration, for k_mrs_vec
+  // this iteration's vector update: p = (v - delta p1 - eps p2) / gamma,
+  // x += ceta p, with v = (stored Lanczos vector) * vnrm_inv
+  double delta, eps, gamma, ceta, vnrm_inv;
+  double inv_beta;          // 1 / beta_{j+1} (normalised vectors)
+  double scaleS, zcoef;     // next product with unnormalised vectors: scaleS (S w_j) + zcoef w_{j-1}
+  double nrm[2];            // norm of the stored vector that represents v_j (slot j&1)
   double bnorm, tol_abs, alpha, minus_one;
   int32_t iter, maxit, done, active, status;  // status: 0 ok, 1 maxit, 2 breakdown, 3 nan
 };
@@ -279,6 +294,10 @@ __device__ __forceinline__ void mrs_update(mrs_dev *d, int par, double sumsq, do
   d->gamma = gamma;
   d->ceta = c * eta;
   d->inv_beta = beta_n > 0.0 ? 1.0 / beta_n : 0.0;
+  d->vnrm_inv = d->nrm[par] > 0.0 ? 1.0 / d->nrm[par] : 0.0;
+  d->scaleS = d->inv_beta;
+  d->zcoef = beta_n * d->vnrm_inv;
+  d->nrm[par ^ 1] = beta_n;
   d->active = 1;
   const double eta_n = -s * eta;
   const int32_t it = d->iter + 1;
@@ -315,6 +334,12 @@ struct prod_task {
   const double *beta;
   double *partials;
   const int32_t *done;
+  const double *scale;   // fused MRS iteration (see epilogue)
+  const double *vec;
+  const int32_t *active;
+  const void *p1;
+  void *p2;
+  void *xs;
 };
 // Fills the layout and value fields of a task for products with vectors of
 // vec_dtype (value_dtype picks FP32 or BF16 values when both are stored, -1:

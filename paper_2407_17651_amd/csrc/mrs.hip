@@ -7,14 +7,17 @@
 // of H_k holds -beta_j (row j-1), alpha (row j) and beta_{j+1} (row j+1).  H_k
 // is reduced by Givens rotations as in MINRES; |eta| is the residual norm.
 //
-// One iteration is three launches on one stream, captured once in a hipGraph
-// (two iterations, because buffer roles alternate) and replayed:
-//   1. the product kernel with the solver epilogue: w = S v_j + beta_j v_{j-1}
-//      and per-tile partial sums of w^2 in FP64 (the inner product);
+// One iteration is two launches on one stream, captured once in a hipGraph
+// (six iterations, the period of the buffer roles) and replayed:
+//   1. the product kernel with the solver epilogue.  Lanczos vectors are kept
+//      unnormalised (W_j = w_j), so the product computes
+//      W_{j+1} = (S W_j) / beta_{j+1} + (beta_{j+1} / beta_j) W_{j-1}
+//      with per-tile partial sums of W_{j+1}^2 in FP64 (the inner product),
+//      and on the same rows applies iteration j's vector update
+//      p_j = (v_j - delta p_{j-1} - eps p_{j-2}) / gamma, x += c eta p_j
+//      with v_j = W_{j-1} / beta_j;
 //   2. k_mrs_scalar, one workgroup: sums the partials in a fixed order,
-//      updates the rotations and eta, records |eta|/||b||, decides to stop;
-//   3. k_mrs_vec: p_j = (v_j - delta p_{j-1} - eps p_{j-2}) / gamma,
-//      x += c eta p_j, v_{j+1} = w / beta_{j+1}.
+//      updates the rotations and eta, records |eta|/||b||, decides to stop.
 // Scalars live on the device; the host reads the stop flag every
 // check_every iterations.  Once stopped, every later kernel returns at once.
 //
@@ -67,17 +70,16 @@ __global__ __launch_bounds__(SB) void k_mrs_scalar(mrs_dev *d, int par, const do
   mrs_update(d, par, sum, hist);
 }
 
+// The vector update of the last iteration when no product carried it:
+// p = (W vnrm_inv - delta p1 - eps p2) / gamma over p2, x += ceta p.
 template <class X>
-__global__ __launch_bounds__(TB) void k_mrs_vec(const mrs_dev *__restrict__ d, int64_t n, const X *__restrict__ v,
-                                               const X *__restrict__ w, const X *__restrict__ p1, X *p2, X *x,
-                                               X *vnext) {
-  if (!d->active) return;
-  const double delta = d->delta, eps = d->eps, gamma = d->gamma, ceta = d->ceta, ib = d->inv_beta;
+__global__ __launch_bounds__(TB) void k_mrs_flush(mrs_dev *d, int64_t n, const X *__restrict__ w,
+                                                 const X *__restrict__ p1, X *p2, X *x) {
+  const double delta = d->delta, eps = d->eps, gamma = d->gamma, ceta = d->ceta, vn = d->vnrm_inv;
   for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
-    const double pn = ((double)v[i] - delta * (double)p1[i] - eps * (double)p2[i]) / gamma;
+    const double pn = ((double)w[i] * vn - delta * (double)p1[i] - eps * (double)p2[i]) / gamma;
     p2[i] = (X)pn;
     x[i] = (X)((double)x[i] + ceta * pn);
-    vnext[i] = (X)((double)w[i] * ib);
   }
 }
 
@@ -151,11 +153,13 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
                                 int32_t *iters, int32_t *status, double *eta_out, double *hist) {
   const int64_t n = A->n;
   const int vec = sizeof(X) == 8 ? PARS3_F64 : PARS3_F32;
-  X *V[2] = {(X *)ws.vb0.p, (X *)ws.vb1.p};
+  // Lanczos vectors are kept unnormalised: W_k = w_k (W_0 = v_1 from the
+  // caller, in ws.vb0), stored in Wb[(k + 1) % 3]; p_k in P[k & 1].  The
+  // product of iteration J computes W_J = scaleS (S W_{J-1}) + zcoef W_{J-2}
+  // and applies iteration J-1's vector update on its rows.
+  X *Wb[3] = {(X *)ws.w.p, (X *)ws.vb0.p, (X *)ws.vb1.p};
   X *P[2] = {(X *)ws.pb0.p, (X *)ws.pb1.p};
-  X *W = (X *)ws.w.p;
-  // state: v_0 = 0, p_0 = p_{-1} = 0, rotations identity, eta = beta_1
-  k_zero<X><<<nblk(n), TB, 0, s>>>(V[1], n);
+  k_zero<X><<<nblk(n), TB, 0, s>>>(Wb[0], n);
   k_zero<X><<<nblk(n), TB, 0, s>>>(P[0], n);
   k_zero<X><<<nblk(n), TB, 0, s>>>(P[1], n);
   P3_LAUNCHED();
@@ -166,6 +170,9 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
   h.c2[0] = 1.0;
   h.s2[0] = 0.0;
   h.eta[0] = beta1;
+  h.nrm[0] = 1.0;  // W_0 = v_1 is normalised
+  h.scaleS = 1.0;
+  h.zcoef = 0.0;
   h.bnorm = bnorm > 0.0 ? bnorm : 1.0;
   h.tol_abs = tol_abs;
   h.alpha = alpha;
@@ -177,25 +184,30 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
   h.status = 0;
   P3_HIP(hipMemcpyAsync(ws.dev.p, &h, sizeof(h), hipMemcpyHostToDevice, s));
   const int32_t np = A->lay.ntiles;
-  // capture two iterations
+  // capture six iterations (buffer roles repeat with period 6)
   const bool prof = A->prof.on;
   A->prof.on = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   pars3_status st = PARS3_OK;
+  mrs_dev *dv = ws.dev.p;
   hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (ce == hipSuccess) {
-    for (int par = 0; par < 2 && st == PARS3_OK; par++) {
+    for (int J = 1; J <= 6 && st == PARS3_OK; J++) {
       epilogue<X> ep;
-      ep.z = V[par ^ 1];
-      ep.beta = &ws.dev.p->beta[par];
+      ep.z = Wb[(J + 2) % 3];
+      ep.beta = &dv->zcoef;
+      ep.scale = &dv->scaleS;
       ep.partials = ws.partials.p;
-      ep.done = &ws.dev.p->done;
-      st = spmv_ex(A, 0.0, V[par], W, 1, vec, value_dtype, s, &ep);
+      ep.done = &dv->done;
+      ep.active = &dv->active;
+      ep.vec = &dv->delta;
+      ep.p1 = P[J & 1];
+      ep.p2 = P[(J + 1) & 1];
+      ep.xs = x;
+      st = spmv_ex(A, 0.0, Wb[J % 3], Wb[(J + 1) % 3], 1, vec, value_dtype, s, &ep);
       if (st != PARS3_OK) break;
-      k_mrs_scalar<<<1, SB, 0, s>>>(ws.dev.p, par, ws.partials.p, np, hist);
-      k_mrs_vec<X><<<std::min<unsigned>(nblk(n), 4096u), TB, 0, s>>>(ws.dev.p, n, V[par], W, P[par], P[par ^ 1], x,
-                                                                        V[par ^ 1]);
+      k_mrs_scalar<<<1, SB, 0, s>>>(dv, (J - 1) & 1, ws.partials.p, np, hist);
     }
     hipError_t ee = hipStreamEndCapture(s, &graph);
     if (st == PARS3_OK && ee != hipSuccess) st = fail(PARS3_EHIP, "mrs: stream capture failed: %s", hipGetErrorString(ee));
@@ -208,8 +220,8 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
     if (ie != hipSuccess) st = fail(PARS3_EHIP, "mrs: graph instantiation failed: %s", hipGetErrorString(ie));
   }
   int32_t done = h.done;
-  const int32_t chunk = std::max(1, check_every / 2);
-  for (int32_t it = 0; st == PARS3_OK && !done && it < maxit; it += 2 * chunk) {
+  const int32_t chunk = std::max(1, check_every / 6);
+  for (int32_t it = 0; st == PARS3_OK && !done && it < maxit; it += 6 * chunk) {
     for (int32_t c = 0; c < chunk; c++) {
       hipError_t le = hipGraphLaunch(exec, s);
       if (le != hipSuccess) {
@@ -218,7 +230,7 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
       }
     }
     if (st != PARS3_OK) break;
-    hipError_t me = hipMemcpyAsync(&h, ws.dev.p, sizeof(h), hipMemcpyDeviceToHost, s);
+    hipError_t me = hipMemcpyAsync(&h, dv, sizeof(h), hipMemcpyDeviceToHost, s);
     if (me == hipSuccess) me = hipStreamSynchronize(s);
     if (me != hipSuccess) st = fail(PARS3_EHIP, "mrs: %s", hipGetErrorString(me));
     done = h.done;
@@ -229,8 +241,14 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
     (void)hipGetLastError();
     return st;
   }
-  P3_HIP(hipMemcpyAsync(&h, ws.dev.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  P3_HIP(hipMemcpyAsync(&h, dv, sizeof(h), hipMemcpyDeviceToHost, s));
   P3_HIP(hipStreamSynchronize(s));
+  if (h.active) {
+    // the last iteration's vector update, when no product followed it
+    const int32_t j = h.iter;
+    k_mrs_flush<X><<<std::min<unsigned>(nblk(n), 4096u), TB, 0, s>>>(dv, n, Wb[j % 3], P[(j + 1) & 1], P[j & 1], x);
+    P3_LAUNCHED();
+  }
   *iters = h.iter;
   *status = h.status;
   *eta_out = std::fabs(h.eta[h.iter & 1]);

@@ -158,6 +158,93 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
     }
 }
 
+// Output phase of a tile (after its LDS row sums are complete): y = shift x
+// + inner band + LDS sum (+ the solver epilogue), one store per row.
+template <class V, class X, int K, bool EP>
+__device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const X (&xown)[K], const double *ys,
+                                           double *s_red) {
+  const V *__restrict__ dia = (const V *)a.dia;
+  const X *__restrict__ x = (const X *)a.x;
+  X *__restrict__ y = (X *)a.y;
+  const X *__restrict__ z = (const X *)a.z;
+  const int32_t n = a.n, w_in = a.w_in;
+  const X shift = (X)a.shift;
+  const int32_t r0 = t << a.lgT;
+  const int32_t rows = min(1 << a.lgT, n - r0);
+  // fused solver iteration: scale of S x, and the pending vector update
+  X sc = (X)1;
+  bool upd = false;
+  double vd = 0.0, ve = 0.0, vg = 1.0, vc = 0.0, vn = 0.0;
+  if constexpr (EP) {
+    if (a.scale) sc = (X)*a.scale;
+    if (K == 1 && a.vec && *a.active) {
+      upd = true;
+      vd = a.vec[0];
+      ve = a.vec[1];
+      vg = a.vec[2];
+      vc = a.vec[3];
+      vn = a.vec[4];
+    }
+  }
+  double sq = 0.0;
+  for (int32_t r = threadIdx.x; r < rows; r += TB) {
+    const int64_t i = r0 + r;
+    X acc[K];
+#pragma unroll
+    for (int c = 0; c < K; c++) acc[c] = (X)ys[r * KP<K> + c];
+    for (int32_t k = 1; k <= w_in; k++) {
+      const int64_t bse = (int64_t)(k - 1) * n;
+      if (i - k >= 0) {
+        const X l = (X)vload<V>::nt(dia, bse + i);
+        if (l != (X)0) {
+#pragma unroll
+          for (int c = 0; c < K; c++) acc[c] += l * x[(i - k) * K + c];
+        }
+      }
+      if (i + k < n) {
+        const X l = (X)vload<V>::nt(dia, bse + i + k);
+        if (l != (X)0) {
+#pragma unroll
+          for (int c = 0; c < K; c++) acc[c] -= l * x[(i + k) * K + c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < K; c++) {
+      const X xi = r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c];
+      acc[c] = EP ? shift * xi + sc * acc[c] : shift * xi + acc[c];
+    }
+    if (EP && z) {
+      const X zb = (X)*a.beta;
+#pragma unroll
+      for (int c = 0; c < K; c++) acc[c] += zb * z[i * K + c];
+      if (upd) {
+        X *__restrict__ p2 = (X *)a.p2;
+        X *__restrict__ xs = (X *)a.xs;
+        const X *__restrict__ p1 = (const X *)a.p1;
+        const double pn = ((double)z[i] * vn - vd * (double)p1[i] - ve * (double)p2[i]) / vg;
+        p2[i] = (X)pn;
+        xs[i] = (X)((double)xs[i] + vc * pn);
+      }
+    }
+    rowvec<X, K>::store(y, i, acc);
+#pragma unroll
+    for (int c = 0; c < K; c++) sq += (double)acc[c] * (double)acc[c];
+  }
+  if (EP && a.partials) {
+    // partial sum of squares of the tile's outputs, in a fixed order
+#pragma unroll
+    for (int d2 = 32; d2 >= 1; d2 >>= 1) sq += __shfl_xor(sq, d2, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < TB / 64; w++) tot += s_red[w];
+      a.partials[t] = tot;
+    }
+  }
+}
+
 // The tile's work list is a list of chunks, runs of at most 64 consecutive
 // entries of one block.  A wavefront takes whole chunks, so a chunk's
 // descriptor (first entry, length, other tile, side) is uniform over the
@@ -207,51 +294,7 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
     chunk_group<V, X, K>(d, lane, lgT, a.ent_rc, ent_v, x, ys);
   }
   __syncthreads();
-  double sq = 0.0;
-  for (int32_t r = threadIdx.x; r < rows; r += TB) {
-    const int64_t i = r0 + r;
-    X acc[K];
-#pragma unroll
-    for (int c = 0; c < K; c++)
-      acc[c] = shift * (r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c]) + (X)ys[r * KP<K> + c];
-    for (int32_t k = 1; k <= w_in; k++) {
-      const int64_t bse = (int64_t)(k - 1) * n;
-      if (i - k >= 0) {
-        const X l = (X)vload<V>::nt(dia, bse + i);
-        if (l != (X)0) {
-#pragma unroll
-          for (int c = 0; c < K; c++) acc[c] += l * x[(i - k) * K + c];
-        }
-      }
-      if (i + k < n) {
-        const X l = (X)vload<V>::nt(dia, bse + i + k);
-        if (l != (X)0) {
-#pragma unroll
-          for (int c = 0; c < K; c++) acc[c] -= l * x[(i + k) * K + c];
-        }
-      }
-    }
-    if (EP && z) {
-      const X zb = (X)*a.beta;
-#pragma unroll
-      for (int c = 0; c < K; c++) acc[c] += zb * z[i * K + c];
-    }
-    rowvec<X, K>::store(y, i, acc);
-#pragma unroll
-    for (int c = 0; c < K; c++) sq += (double)acc[c] * (double)acc[c];
-  }
-  if (EP && a.partials) {
-    // partial sum of squares of the tile's outputs, in a fixed order
-#pragma unroll
-    for (int d2 = 32; d2 >= 1; d2 >>= 1) sq += __shfl_xor(sq, d2, 64);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = sq;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (int w = 0; w < TB / 64; w++) tot += s_red[w];
-      a.partials[t] = tot;
-    }
-  }
+  tile_final<V, X, K, EP>(a, t, xown, ys, s_red);
 }
 
 // One matrix: one workgroup per tile.  EP: with the solver epilogue (a
@@ -260,7 +303,9 @@ template <class V, class X, int K, bool EP>
 __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   __shared__ double s_red[TB / 64];
   extern __shared__ double ys[];
-  if (EP && a.done && *a.done) return;
+  // a finished solver skips its remaining products, except the one that
+  // still carries its last vector update
+  if (EP && a.done && *a.done && !(a.active && *a.active)) return;
   const int32_t t = xcd_tile(blockIdx.x, a.ntiles);
   if (t >= a.ntiles) return;
   tile_body<V, X, K, EP>(a, t, ys, s_red);
@@ -284,7 +329,7 @@ __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restric
   for (int32_t it = qbeg[q] + j; it < end; it += J) {
     const int2 w = items[it];
     const prod_task &a = tasks[w.x];
-    if (EP && a.done && *a.done) continue;
+    if (EP && a.done && *a.done && !(a.active && *a.active)) continue;
     tile_body<V, X, K, EP>(a, w.y, ys, s_red);
     __syncthreads();  // ys and s_red are reused by the next item
   }
@@ -327,8 +372,14 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   a.beta = ep.beta;
   a.partials = ep.partials;
   a.done = ep.done;
-  const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
+  a.scale = ep.scale;
+  a.vec = ep.vec;
+  a.active = ep.active;
+  a.p1 = ep.p1;
+  a.p2 = ep.p2;
+  a.xs = ep.xs;
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
+  const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
   k_tile_product<V, X, K, EP><<<grid, TB, lds, s>>>(a);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
