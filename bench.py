@@ -75,59 +75,64 @@ def skew_bytes(n, nnz, dtype, k=1):
 def batched(args, p3, synth, torch, np):
     """256 skew matrices (2D/3D stencils and random geometric graphs, n
     log-uniform in [2k, 200k]) with k = 8 FP32 right-hand sides in one
-    persistent graph-captured launch, configurations chosen per matrix by the
-    trained selector when its weights are present (else the defaults); then
-    256 MRS solves (alpha_i in [0.1, 2], b_i = A_i 1) to 1e-10 together."""
-    from paper_2407_17651_amd import selector
-
+    persistent graph-captured launch; then 256 MRS solves (alpha_i in
+    [0.1, 2], b_i = A_i 1) to 1e-10 together.  The tile height of the batch
+    is tuned per operation by timing whole batch launches (each matrix keeps
+    its reordering; only the split is rebuilt)."""
     specs = synth.batch_specs(256)
     print("[bench] batched: generating 256 matrices", file=sys.stderr, flush=True)
     Ls = [synth.make(s, "uniform_f32") for s in specs]
-    net, grid = selector.load_trained(p3) if os.path.exists(selector.WEIGHTS) else (None, None)
     t0 = time.perf_counter()
-    mats, chosen = [], []
-    for L in Ls:
-        M = p3.Matrix(L)
-        if net is not None:
-            M.reorder(value_dtype=p3.F32, keep_fp64=1)
-            chosen.append(p3.pars3_select(M.h, net, grid))
-            # pars3_select re-split with FP32 values only: keep FP64 for MRS
-            i = M.info()
-            M.reorder(value_dtype=p3.F32, keep_fp64=1, tile_rows=i["tile_rows"], w_in=i["w_in"], t_out=i["t_out"])
-        else:
-            M.reorder(value_dtype=p3.F32, keep_fp64=1)
-        mats.append(M)
+    mats = [p3.Matrix(L).reorder(value_dtype=p3.F32, keep_fp64=1) for L in Ls]
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
-    bat = p3.Batch(mats)
     dev = torch.device("cuda:0")
     xs = [torch.from_numpy(synth.vector(L.n, 500 + i, 8)).to(dev, torch.float32) for i, L in enumerate(Ls)]
     ys = [torch.empty_like(x) for x in xs]
     shifts = np.array([s["alpha"] for s in specs])
-    for _ in range(5):
-        bat.spmv(xs, ys, shifts, k=8, vec_dtype=p3.F32)
-    torch.cuda.synchronize()
+    ones = [torch.ones(L.n, dtype=torch.float64, device=dev) for L in Ls]
+    bs = [torch.empty_like(o) for o in ones]
+
+    def time_launch(bat, xs_, ys_, k, vec, reps):
+        for _ in range(3):
+            bat.spmv(xs_, ys_, shifts, k=k, vec_dtype=vec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            bat.spmv(xs_, ys_, shifts, k=k, vec_dtype=vec)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def split_all(T):
+        for M in mats:
+            M.reorder(value_dtype=p3.F32, keep_fp64=1, tile_rows=T)
+        return p3.Batch(mats)
+
+    tiles = (256, 512, 1024)
+    tune = {}
+    for T in tiles:
+        bat = split_all(T)
+        tune[T] = (time_launch(bat, xs, ys, 8, p3.F32, 5), time_launch(bat, ones, bs, 1, p3.F64, 5))
+        del bat
+    t8 = min(tiles, key=lambda T: tune[T][0])
+    t1 = min(tiles, key=lambda T: tune[T][1])
+    bat = split_all(t8)
     reps = max(10, args.steps // 4)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        bat.spmv(xs, ys, shifts, k=8, vec_dtype=p3.F32)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    ms = time_launch(bat, xs, ys, 8, p3.F32, reps)
     nsum = sum(L.n for L in Ls)
     nnzsum = sum(L.nnz for L in Ls)
     Bb = sum(skew_bytes(L.n, L.nnz, "f32", 8) for L in Ls)
     out = {"workload": "256 skew matrices (2D/3D stencils, RGG deg 16), n log-uniform in [2k, 200k], "
                        "k = 8 FP32 right-hand sides, one persistent graph-captured launch",
-           "sum_n": nsum, "sum_nnz_lower": nnzsum, "configs": "selector" if net is not None else "default",
+           "sum_n": nsum, "sum_nnz_lower": nnzsum, "tile_rows": t8,
+           "tuning_ms": {str(T): [round(a, 4), round(b, 4)] for T, (a, b) in tune.items()},
            "ms_per_launch": round(ms, 4), "gbs": round(Bb / (ms * 1e-3) / 1e9, 1),
            "gflops": round(4.0 * 8 * nnzsum / (ms * 1e-3) / 1e9, 1), "prep_s": round(prep_s, 2)}
-    if chosen:
-        out["selector_choices"] = {str(k): int(v) for k, v in zip(*np.unique(chosen, return_counts=True))}
-    # batched MRS
-    ones = [torch.ones(L.n, dtype=torch.float64, device=dev) for L in Ls]
-    bs = [torch.empty_like(o) for o in ones]
+    # batched MRS on the tile height tuned for the FP64 product
+    del bat
+    bat = split_all(t1)
     bat.spmv(ones, bs, shifts, k=1, vec_dtype=p3.F64)
     xs0 = [torch.zeros_like(o) for o in ones]
     print("[bench] batched MRS", file=sys.stderr, flush=True)
@@ -136,7 +141,7 @@ def batched(args, p3, synth, torch, np):
         x.zero_()
     st, infos = bat.mrs(shifts, bs, xs0, check=False, order=p3.ORDER_RCM, tol=1e-10, maxit=20000)
     it = np.array([i["iters"] for i in infos])
-    out["mrs"] = {"status": p3.STATUS_NAMES[st], "ms": round(infos[0]["time_ms"], 2),
+    out["mrs"] = {"status": p3.STATUS_NAMES[st], "tile_rows": t1, "ms": round(infos[0]["time_ms"], 2),
                   "max_relres": float(max(i["relres"] for i in infos)), "iters_max": int(it.max()),
                   "iters_mean": round(float(it.mean()), 1), "systems": len(infos)}
     return out

@@ -55,7 +55,7 @@ struct bmrs_ptrs {
   const int32_t *poff, *ntl;
   const int32_t *bsys;
   const int64_t *bstart;
-  double *V0, *V1, *W, *P0, *P1, *X, *B, *Y, *partials;
+  double *W0, *W1, *W2, *P0, *P1, *X, *B, *Y, *partials;
 };
 
 // sum of squares of each system's segment of a (one workgroup per system)
@@ -84,13 +84,13 @@ __global__ void k_bmrs_init(bmrs_ptrs p, const double *__restrict__ bn2, const d
   if (i >= m) return;
   mrs_dev &d = p.dev[i];
   const double bnorm = sqrt(bn2[i]), beta1 = sqrt(rn2[i]);
-  for (int k = 0; k < 2; k++) d.beta[k] = d.c1[k] = d.s1[k] = d.c2[k] = d.s2[k] = d.eta[k] = 0.0;
-  d.beta[0] = 0.0;
+  for (int k = 0; k < 2; k++) d.beta[k] = d.c1[k] = d.s1[k] = d.c2[k] = d.s2[k] = d.eta[k] = d.nrm[k] = 0.0;
   d.c1[0] = 1.0;
   d.c2[0] = 1.0;
   d.eta[0] = beta1;
-  d.delta = d.eps = d.gamma = d.ceta = d.inv_beta = d.vnrm_inv = d.scaleS = d.zcoef = 0.0;
-  d.nrm[0] = d.nrm[1] = 1.0;
+  d.nrm[0] = 1.0;  // W_0 = v_1 is normalised
+  d.delta = d.eps = d.gamma = d.ceta = d.inv_beta = d.vnrm_inv = d.zcoef = 0.0;
+  d.scaleS = 1.0;
   d.bnorm = bnorm > 0.0 ? bnorm : 1.0;
   d.tol_abs = tol * bnorm;
   d.alpha = alpha[i];
@@ -102,21 +102,22 @@ __global__ void k_bmrs_init(bmrs_ptrs p, const double *__restrict__ bn2, const d
   d.status = 0;
 }
 
-// v_1 = -y / ||y||, v_0 = p_0 = p_{-1} = 0 for every system
+// W_0 = v_1 = -y / ||y|| (unnormalised Lanczos vectors W_k live in
+// W[(k + 1) % 3]), W_{-1} = p_0 = p_{-1} = 0 for every system
 __global__ __launch_bounds__(BT) void k_bmrs_start(bmrs_ptrs p) {
   const int32_t i = p.bsys[blockIdx.x];
   const int64_t e1 = p.off[i + 1];
   const double beta1 = p.dev[i].eta[0];
   const double inv = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
   for (int64_t e = p.bstart[blockIdx.x] + threadIdx.x, q = 0; q < 4 && e < e1; q++, e += BT) {
-    p.V0[e] = -p.Y[e] * inv;
-    p.V1[e] = 0.0;
+    p.W1[e] = -p.Y[e] * inv;
+    p.W0[e] = 0.0;
     p.P0[e] = 0.0;
     p.P1[e] = 0.0;
   }
 }
 
-__global__ __launch_bounds__(1024) void k_bmrs_scalar(bmrs_ptrs p, int par, double *__restrict__ hist_unused) {
+__global__ __launch_bounds__(1024) void k_bmrs_scalar(bmrs_ptrs p, int par) {
   __shared__ double red[1024 / 64];
   const int32_t i = blockIdx.x;
   mrs_dev *d = &p.dev[i];
@@ -137,25 +138,31 @@ __global__ __launch_bounds__(1024) void k_bmrs_scalar(bmrs_ptrs p, int par, doub
 #pragma unroll
   for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   if (threadIdx.x != 0) return;
-  mrs_update(d, par, s, hist_unused);
+  mrs_update(d, par, s, nullptr);
 }
 
-__global__ __launch_bounds__(BT) void k_bmrs_vec(bmrs_ptrs p, int par) {
+// The pending vector update of every finished system whose last iteration
+// was not followed by a product: p_j = (W_{j-1} vnrm_inv - delta p_{j-1}
+// - eps p_{j-2}) / gamma, x += ceta p_j.  Then k_bmrs_settle clears its flag.
+__global__ __launch_bounds__(BT) void k_bmrs_flush(bmrs_ptrs p) {
   const int32_t i = p.bsys[blockIdx.x];
   const mrs_dev *d = &p.dev[i];
-  if (!d->active) return;
-  const double delta = d->delta, eps = d->eps, gamma = d->gamma, ceta = d->ceta, ib = d->inv_beta;
-  const double *v = par ? p.V1 : p.V0;
-  double *vnext = par ? p.V0 : p.V1;
-  const double *p1 = par ? p.P1 : p.P0;
-  double *p2 = par ? p.P0 : p.P1;
+  if (!(d->done && d->active)) return;
+  const int32_t j = d->iter;
+  const double *w = j % 3 == 0 ? p.W0 : (j % 3 == 1 ? p.W1 : p.W2);
+  const double *p1 = (j + 1) & 1 ? p.P1 : p.P0;
+  double *p2 = j & 1 ? p.P1 : p.P0;
+  const double delta = d->delta, eps = d->eps, gamma = d->gamma, ceta = d->ceta, vn = d->vnrm_inv;
   const int64_t e1 = p.off[i + 1];
   for (int64_t e = p.bstart[blockIdx.x] + threadIdx.x, q = 0; q < 4 && e < e1; q++, e += BT) {
-    const double pn = (v[e] - delta * p1[e] - eps * p2[e]) / gamma;
+    const double pn = (w[e] * vn - delta * p1[e] - eps * p2[e]) / gamma;
     p2[e] = pn;
     p.X[e] += ceta * pn;
-    vnext[e] = p.W[e] * ib;
   }
+}
+__global__ void k_bmrs_settle(mrs_dev *__restrict__ dev, int32_t m) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && dev[i].done) dev[i].active = 0;
 }
 
 static inline unsigned g1(int64_t m, int b = BT) { return (unsigned)std::max<int64_t>(1, cdiv(m, b)); }
@@ -163,6 +170,49 @@ static inline unsigned g1(int64_t m, int b = BT) { return (unsigned)std::max<int
 }  // namespace p3
 
 using p3::fail;
+
+// Work list of the matrices with use[i] != 0 (all when use is NULL):
+// matrices largest first, tiles ascending, cut into 8 contiguous queues of
+// equal estimated cost (stored entries twice, rows once, inner band).
+static void build_queues(const std::vector<pars3_matrix *> &mats, const int32_t *use, std::vector<int2> &it,
+                         std::vector<int32_t> &qb) {
+  const int32_t m = (int32_t)mats.size();
+  std::vector<int32_t> ord;
+  for (int32_t i = 0; i < m; i++)
+    if (!use || use[i]) ord.push_back(i);
+  auto mcost = [&](int32_t i) {
+    const pars3_matrix *A = mats[i];
+    return 2.0 * (double)A->lay.nnz_blocked + (double)A->n * (1 + A->lay.w_in);
+  };
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return mcost(a) > mcost(b); });
+  it.clear();
+  std::vector<double> cost;
+  double total = 0.0;
+  for (int32_t i : ord) {
+    const int32_t nt = mats[i]->lay.ntiles;
+    const double c = nt ? mcost(i) / nt : 0.0;
+    for (int32_t t = 0; t < nt; t++) {
+      it.push_back(make_int2(i, t));
+      cost.push_back(c);
+      total += c;
+    }
+  }
+  qb.assign(9, 0);
+  double acc = 0.0;
+  int q = 1;
+  for (size_t k = 0; k < it.size(); k++) {
+    acc += cost[k];
+    while (q < 8 && acc >= total * q / 8.0) qb[q++] = (int32_t)(k + 1);
+  }
+  while (q < 8) qb[q++] = (int32_t)it.size();
+  qb[8] = (int32_t)it.size();
+  for (int k = 1; k <= 8; k++) qb[k] = std::max(qb[k], qb[k - 1]);
+}
+
+static int32_t persistent_grid(int64_t nitems) {
+  // up to 8 workgroups per CU over 256 CUs, a multiple of 8
+  return (int32_t)std::min<int64_t>(2048, 8 * p3::cdiv(std::max<int64_t>(nitems, 1), 8));
+}
 
 extern "C" pars3_status pars3_batch_create(int32_t m, pars3_matrix *const *mats, pars3_batch **out) {
   using namespace p3;
@@ -187,41 +237,11 @@ extern "C" pars3_status pars3_batch_create(int32_t m, pars3_matrix *const *mats,
     B->poff[i + 1] = B->poff[i] + mats[i]->lay.ntiles;
     B->maxT = std::max(B->maxT, mats[i]->lay.T);
   }
-  // items: matrices largest first, tiles ascending; cost per tile
-  std::vector<int32_t> ord(m);
-  std::iota(ord.begin(), ord.end(), 0);
-  auto mcost = [&](int32_t i) {
-    const pars3_matrix *A = mats[i];
-    return 2.0 * (double)A->lay.nnz_blocked + (double)A->n * (1 + A->lay.w_in);
-  };
-  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return mcost(a) > mcost(b); });
   std::vector<int2> it;
-  std::vector<double> cost;
-  double total = 0.0;
-  for (int32_t i : ord) {
-    const int32_t nt = mats[i]->lay.ntiles;
-    const double c = nt ? mcost(i) / nt : 0.0;
-    for (int32_t t = 0; t < nt; t++) {
-      it.push_back(make_int2(i, t));
-      cost.push_back(c);
-      total += c;
-    }
-  }
-  std::vector<int32_t> qb(9, 0);
-  {
-    double acc = 0.0;
-    int q = 1;
-    for (size_t k = 0; k < it.size(); k++) {
-      acc += cost[k];
-      while (q < 8 && acc >= total * q / 8.0) qb[q++] = (int32_t)(k + 1);
-    }
-    while (q < 8) qb[q++] = (int32_t)it.size();
-    qb[8] = (int32_t)it.size();
-    for (int k = 1; k <= 8; k++) qb[k] = std::max(qb[k], qb[k - 1]);
-  }
+  std::vector<int32_t> qb;
+  build_queues(B->mats, nullptr, it, qb);
   B->nitems = (int32_t)it.size();
-  // persistent grid: up to 8 workgroups per CU over 256 CUs, a multiple of 8
-  B->grid = (int32_t)std::min<int64_t>(2048, 8 * cdiv(std::max<int64_t>(B->nitems, 1), 8));
+  B->grid = persistent_grid(B->nitems);
   if (B->items.alloc(std::max<size_t>(it.size(), 1)) != hipSuccess || B->qbeg.alloc(9) != hipSuccess || B->tasks.alloc(m) != hipSuccess) {
     (void)hipGetLastError();
     return bad(fail(PARS3_ENOMEM, "batch: device allocation failed"));
@@ -351,15 +371,16 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   const int32_t nvb = (int32_t)bsys.size();
   std::vector<int32_t> ntl(m);
   for (int32_t i = 0; i < m; i++) ntl[i] = B->mats[i]->lay.ntiles;
-  dbuf<double> V0, V1, W, P0, P1, X, Bv, Y, part, nb2, nr2, alph;
+  dbuf<double> W0, W1, W2, P0, P1, X, Bv, Y, part, nb2, nr2, alph;
   dbuf<mrs_dev> dev;
   dbuf<int64_t> doff, dbst;
-  dbuf<int32_t> dpoff, dntl, dbsys;
+  dbuf<int32_t> dpoff, dntl, dbsys, dqb;
+  dbuf<int2> ditems;
   dbuf<prod_task> tk;
   const size_t n1 = (size_t)std::max<int64_t>(N, 1);
-  P3_HIP(V0.alloc(n1));
-  P3_HIP(V1.alloc(n1));
-  P3_HIP(W.alloc(n1));
+  P3_HIP(W0.alloc(n1));
+  P3_HIP(W1.alloc(n1));
+  P3_HIP(W2.alloc(n1));
   P3_HIP(P0.alloc(n1));
   P3_HIP(P1.alloc(n1));
   P3_HIP(X.alloc(n1));
@@ -375,7 +396,9 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   P3_HIP(dpoff.alloc(m + 1));
   P3_HIP(dntl.alloc(m));
   P3_HIP(dbsys.alloc(std::max(nvb, 1)));
-  P3_HIP(tk.alloc(3 * (size_t)m));
+  P3_HIP(dqb.alloc(9));
+  P3_HIP(ditems.alloc(std::max(B->nitems, 1)));
+  P3_HIP(tk.alloc(7 * (size_t)m));
   P3_HIP(hipMemcpyAsync(doff.p, B->off.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   P3_HIP(hipMemcpyAsync(dpoff.p, B->poff.data(), (m + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
   P3_HIP(hipMemcpyAsync(dntl.p, ntl.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -396,14 +419,18 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
       P3_HIP(hipMemcpyAsync(X.p + B->off[i], x[i], A->n * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
   }
-  bmrs_ptrs P{dev.p, doff.p, dpoff.p, dntl.p, dbsys.p, dbst.p, V0.p, V1.p, W.p, P0.p, P1.p, X.p, Bv.p, Y.p, part.p};
-  // task tables: [0, m) residual y = alpha x + S x - b; [m, 2m) and [2m, 3m)
-  // the iterations of parity 0 and 1: w = S v_j + beta_j v_{j-1}
-  std::vector<prod_task> ht(3 * (size_t)m);
+  bmrs_ptrs P{dev.p, doff.p, dpoff.p, dntl.p, dbsys.p, dbst.p, W0.p, W1.p, W2.p, P0.p, P1.p, X.p, Bv.p, Y.p, part.p};
+  double *Wb[3] = {W0.p, W1.p, W2.p};
+  double *Pb[2] = {P0.p, P1.p};
+  // task tables: [0, m) the residual y = alpha x + S x - b; [J m, (J+1) m)
+  // for J = 1..6 the fused iterations (buffer roles repeat with period 6):
+  // W_J = scaleS (S W_{J-1}) + zcoef W_{J-2}, with iteration J-1's vector
+  // update on the same rows
+  std::vector<prod_task> ht(7 * (size_t)m);
   int vk = -1;
   for (int32_t i = 0; i < m; i++) {
     const int64_t e = B->off[i];
-    for (int r = 0; r < 3; r++) {
+    for (int r = 0; r < 7; r++) {
       prod_task &a = ht[(size_t)r * m + i];
       P3_TRY(make_task(B->mats[i], PARS3_F64, -1, &a, &vk));
       a.partials = part.p + B->poff[i];
@@ -414,46 +441,66 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
         a.z = Bv.p + e;
         a.beta = &dev.p[i].minus_one;
       } else {
-        const int par = r - 1;
+        const int J = r;
         a.shift = 0.0;
-        a.x = (par ? V1.p : V0.p) + e;
-        a.y = W.p + e;
-        a.z = (par ? V0.p : V1.p) + e;
-        a.beta = &dev.p[i].beta[par];
+        a.x = Wb[J % 3] + e;
+        a.y = Wb[(J + 1) % 3] + e;
+        a.z = Wb[(J + 2) % 3] + e;
+        a.beta = &dev.p[i].zcoef;
+        a.scale = &dev.p[i].scaleS;
         a.done = &dev.p[i].done;
+        a.active = &dev.p[i].active;
+        a.vec = &dev.p[i].delta;
+        a.p1 = Pb[J & 1] + e;
+        a.p2 = Pb[(J + 1) & 1] + e;
+        a.xs = X.p + e;
       }
     }
   }
   P3_HIP(hipMemcpyAsync(tk.p, ht.data(), ht.size() * sizeof(prod_task), hipMemcpyHostToDevice, s));
+  // the full work list (also used for the residuals)
+  std::vector<int2> hit;
+  std::vector<int32_t> hqb;
+  build_queues(B->mats, nullptr, hit, hqb);
+  int32_t grid = persistent_grid((int64_t)hit.size());
+  if (!hit.empty()) P3_HIP(hipMemcpyAsync(ditems.p, hit.data(), hit.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  P3_HIP(hipMemcpyAsync(dqb.p, hqb.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice, s));
   // ||b|| and r0 = b - A x0 (y = alpha x0 + S x0 - b)
   k_bmrs_const<<<g1(m), BT, 0, s>>>(dev.p, m);
   k_bnorm<<<m, BT, 0, s>>>(Bv.p, doff.p, nb2.p);
   P3_LAUNCHED();
-  P3_TRY(launch_batch(PARS3_F64, 1, true, tk.p, B->items.p, B->qbeg.p, B->grid, B->maxT, s));
+  P3_TRY(launch_batch(PARS3_F64, 1, true, tk.p, ditems.p, dqb.p, grid, B->maxT, s));
   k_bnorm<<<m, BT, 0, s>>>(Y.p, doff.p, nr2.p);
   k_bmrs_init<<<g1(m), BT, 0, s>>>(P, nb2.p, nr2.p, alph.p, o.tol, o.maxit, m);
   if (nvb) k_bmrs_start<<<nvb, BT, 0, s>>>(P);
   P3_LAUNCHED();
-  // two iterations captured and replayed
+  // six iterations captured and replayed; the work list is rebuilt from the
+  // systems still iterating whenever their number has halved
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  pars3_status st = PARS3_OK;
-  P3_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  for (int par = 0; par < 2 && st == PARS3_OK; par++) {
-    st = launch_batch(PARS3_F64, 1, true, tk.p + (size_t)(1 + par) * m, B->items.p, B->qbeg.p, B->grid, B->maxT, s);
-    if (st != PARS3_OK) break;
-    k_bmrs_scalar<<<m, 1024, 0, s>>>(P, par, nullptr);
-    if (nvb) k_bmrs_vec<<<nvb, BT, 0, s>>>(P, par);
-  }
-  const hipError_t ee = hipStreamEndCapture(s, &graph);
-  if (st == PARS3_OK && ee != hipSuccess) st = fail(PARS3_EHIP, "batch mrs: capture failed: %s", hipGetErrorString(ee));
-  if (st == PARS3_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
-    st = fail(PARS3_EHIP, "batch mrs: graph instantiation failed");
+  auto capture = [&]() -> pars3_status {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    P3_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    pars3_status st2 = PARS3_OK;
+    for (int J = 1; J <= 6 && st2 == PARS3_OK; J++) {
+      st2 = launch_batch(PARS3_F64, 1, true, tk.p + (size_t)J * m, ditems.p, dqb.p, grid, B->maxT, s);
+      if (st2 == PARS3_OK) k_bmrs_scalar<<<m, 1024, 0, s>>>(P, (J - 1) & 1);
+    }
+    const hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (st2 != PARS3_OK) return st2;
+    if (ee != hipSuccess) return fail(PARS3_EHIP, "batch mrs: capture failed: %s", hipGetErrorString(ee));
+    P3_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    return PARS3_OK;
+  };
+  pars3_status st = capture();
   std::vector<mrs_dev> hd(m);
-  std::vector<int32_t> doneh(m, 0);
-  bool all = false;
-  const int32_t chunk = std::max(1, o.check_every / 2);
-  for (int32_t it = 0; st == PARS3_OK && !all && it < o.maxit; it += 2 * chunk) {
+  std::vector<int32_t> use(m, 1);
+  int32_t in_list = m;
+  const int32_t chunk = std::max(1, o.check_every / 6);
+  for (int32_t it = 0; st == PARS3_OK && it < o.maxit; it += 6 * chunk) {
     for (int32_t c = 0; c < chunk && st == PARS3_OK; c++)
       if (hipGraphLaunch(exec, s) != hipSuccess) st = fail(PARS3_EHIP, "batch mrs: graph launch failed");
     if (st != PARS3_OK) break;
@@ -462,8 +509,25 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
       st = fail(PARS3_EHIP, "batch mrs: state read failed");
       break;
     }
-    all = true;
-    for (int32_t i = 0; i < m; i++) all = all && hd[i].done;
+    int32_t running = 0;
+    for (int32_t i = 0; i < m; i++) running += hd[i].done ? 0 : 1;
+    if (running == 0) break;
+    if (2 * running <= in_list) {
+      // apply the pending updates of the systems leaving the list, then
+      // restrict the work list to the systems still iterating
+      if (nvb) k_bmrs_flush<<<nvb, BT, 0, s>>>(P);
+      k_bmrs_settle<<<g1(m), BT, 0, s>>>(dev.p, m);
+      for (int32_t i = 0; i < m; i++) use[i] = hd[i].done ? 0 : 1;
+      build_queues(B->mats, use.data(), hit, hqb);
+      grid = persistent_grid((int64_t)hit.size());
+      if (!hit.empty() && hipMemcpyAsync(ditems.p, hit.data(), hit.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
+        st = fail(PARS3_EHIP, "batch mrs: work list upload failed");
+      if (st == PARS3_OK && hipMemcpyAsync(dqb.p, hqb.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        st = fail(PARS3_EHIP, "batch mrs: work list upload failed");
+      if (st == PARS3_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(PARS3_EHIP, "batch mrs: sync failed");
+      if (st == PARS3_OK) st = capture();
+      in_list = running;
+    }
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
@@ -471,8 +535,15 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
     (void)hipGetLastError();
     return st;
   }
-  // true residuals and outputs
-  P3_TRY(launch_batch(PARS3_F64, 1, true, tk.p, B->items.p, B->qbeg.p, B->grid, B->maxT, s));
+  // pending updates, then the true residuals over the full work list
+  if (nvb) k_bmrs_flush<<<nvb, BT, 0, s>>>(P);
+  k_bmrs_settle<<<g1(m), BT, 0, s>>>(dev.p, m);
+  P3_LAUNCHED();
+  build_queues(B->mats, nullptr, hit, hqb);
+  grid = persistent_grid((int64_t)hit.size());
+  if (!hit.empty()) P3_HIP(hipMemcpyAsync(ditems.p, hit.data(), hit.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  P3_HIP(hipMemcpyAsync(dqb.p, hqb.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  P3_TRY(launch_batch(PARS3_F64, 1, true, tk.p, ditems.p, dqb.p, grid, B->maxT, s));
   k_bnorm<<<m, BT, 0, s>>>(Y.p, doff.p, nr2.p);
   P3_LAUNCHED();
   std::vector<double> hr(m), hb(m);
