@@ -168,3 +168,24 @@ def test_workload1_full_size_fp64():
     print("[gpu] spmv workload1 fp64", flush=True)
     M, err = check_product(L, shift=0.5, value_dtype=p3.F64, seed=1101)
     print(f"[gpu] workload1 fp64 rel err {err:.3e}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def workload2():
+    L = synth.workload(2)
+    return L, oracle.permute(L, oracle.rcm(L))
+
+
+@pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32])
+def test_workload2_full_size(workload2, value_dtype):
+    """Random geometric graph, n = 4M, mean degree 16, in full: every output
+    against the oracle."""
+    L, B = workload2
+    print(f"[gpu] spmv workload2 n={L.n} nnz={L.nnz} dtype={value_dtype}", flush=True)
+    M = p3.Matrix(L).reorder(value_dtype=value_dtype)
+    x = synth.vector(L.n, 12)
+    vec = p3.F64 if value_dtype == p3.F64 else p3.F32
+    xr = x if vec == p3.F64 else x.astype(np.float32).astype(np.float64)
+    Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, "f64" if vec == p3.F64 else "f32")})
+    want = oracle.spmv(Bv, 0.25, xr)
+    assert rel_inf(gpu_spmv(M, 0.25, x, vec), want) <= TOL[value_dtype]

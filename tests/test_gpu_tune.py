@@ -19,7 +19,7 @@ def test_default_grid():
         (T, w, t) for T in (64, 128, 256, 512, 1024) for w in (0, 1, 2, 4) for t in (-1, -2)}
 
 
-@pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32])
+@pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32, p3.BF16])
 def test_autotune_picks_fastest_and_leaves_it_applied(value_dtype):
     L = synth.rgg2d(40000, 12.0, 3)
     print(f"[gpu] autotune rgg dtype={value_dtype}", flush=True)
@@ -39,7 +39,8 @@ def test_autotune_picks_fastest_and_leaves_it_applied(value_dtype):
     x = synth.vector(L.n, 2)
     vec = p3.F64 if value_dtype == p3.F64 else p3.F32
     xr = x if vec == p3.F64 else x.astype(np.float32).astype(np.float64)
-    Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, "f64" if vec == p3.F64 else "f32")})
+    kind = {p3.F64: "f64", p3.F32: "f32", p3.BF16: "bf16"}[value_dtype]
+    Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, kind)})
     assert rel_inf(gpu_spmv(M, 0.5, x, vec), oracle.spmv(Bv, 0.5, xr)) <= (1e-12 if vec == p3.F64 else 1e-5)
 
 
