@@ -162,9 +162,13 @@ extern "C" pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x,
     P3_HIP(A->xr.alloc(bytes));
     P3_HIP(A->yr.alloc(bytes));
   }
+  P3_TRY(p3::prof_mark(A, p3::PROF_FIXUP, 0, s));
   P3_TRY(p3::gather_rows(x, A->xr.p, A->perm.p, A->n, k, elem, s));
+  P3_TRY(p3::prof_mark(A, p3::PROF_FIXUP, 1, s));
   P3_TRY(p3::spmv_rcm(A, shift, A->xr.p, A->yr.p, k, vec_dtype, s));
+  P3_TRY(p3::prof_mark(A, p3::PROF_FIXUP, 0, s));
   P3_TRY(p3::scatter_rows(A->yr.p, y, A->perm.p, A->n, k, elem, s));
+  P3_TRY(p3::prof_mark(A, p3::PROF_FIXUP, 1, s));
   return PARS3_OK;
 }
 

@@ -189,3 +189,22 @@ def test_workload2_full_size(workload2, value_dtype):
     Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, "f64" if vec == p3.F64 else "f32")})
     want = oracle.spmv(Bv, 0.25, xr)
     assert rel_inf(gpu_spmv(M, 0.25, x, vec), want) <= TOL[value_dtype]
+
+
+def test_profiling_counters():
+    L = synth.grid3d(20, 2)
+    M = p3.Matrix(L).reorder()
+    x = to_dev(synth.vector(L.n, 1))
+    y = torch.empty_like(x)
+    p3.pars3_set_profiling(M.h, True)
+    for _ in range(3):
+        p3.pars3_spmv(M.h, 0.5, x, y, 1, p3.F64, p3.ORDER_RCM)
+    pr = p3.pars3_get_profile(M.h)
+    assert pr["calls"] == 3 and pr["ms_band"] > 0 and pr["ms_fixup"] == 0
+    p3.pars3_spmv(M.h, 0.5, x, y, 1, p3.F64, p3.ORDER_ORIGINAL)
+    pr = p3.pars3_get_profile(M.h)
+    assert pr["calls"] == 1 and pr["ms_band"] > 0 and pr["ms_fixup"] > 0
+    assert p3.pars3_get_profile(M.h)["calls"] == 0  # reset by the read
+    p3.pars3_set_profiling(M.h, False)
+    p3.pars3_spmv(M.h, 0.5, x, y, 1, p3.F64, p3.ORDER_RCM)
+    assert p3.pars3_get_profile(M.h)["calls"] == 0
