@@ -12,8 +12,11 @@
 // contiguous, and inside a block the entries of one column are contiguous.
 // Each entry stores ((i - t*T) << 16 | (j - u*T)) and its value.  Per row
 // tile: its block range; per column tile: the list of blocks whose column tile
-// it is.  All placement is a stable radix sort plus prefix sums, so the layout
-// is deterministic.
+// it is.  The product reads, per tile, its own blocks (row side) and the
+// blocks of its column list (column side), cut into chunks of at most 64
+// consecutive entries; the first CHUNKS_FIXED chunk descriptors of a tile sit
+// at fixed positions, the rest in an overflow list.  All placement is a stable
+// radix sort plus prefix sums, so the layout is deterministic.
 #include <algorithm>
 
 #include "internal.h"

@@ -19,13 +19,16 @@
 //   2. k_mrs_scalar, one workgroup: sums the partials in a fixed order,
 //      updates the rotations and eta, records |eta|/||b||, decides to stop.
 // Scalars live on the device; the host reads the stop flag every
-// check_every iterations.  Once stopped, every later kernel returns at once.
+// check_every iterations.  Once stopped, the next product still applies the
+// last vector update (or k_mrs_flush does, when no product followed within
+// the replay) and every later kernel returns at once.
 //
 // Mixed precision: iterative refinement in FP64 around an inner MRS whose
 // matrix values and vectors are FP32 (or BF16 values with FP32 vectors) while
 // its inner products and scalars stay FP64:
 //   r = b - A x (FP64 values and vectors); stop when ||r|| <= tol ||b||;
-//   solve (alpha*I + S~) d = r to relative tolerance inner_tol; x += d.
+//   solve (alpha*I + S~) d = r to relative tolerance max(inner_tol,
+//   0.3 tol ||b|| / ||r||) (no tighter than the outer target needs); x += d.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
