@@ -10,7 +10,8 @@ library under ``paper_2407_17651_amd`` and never imports it.
 
 Matrices are passed as any object with ``n``, ``rowptr`` (int32[n+1]),
 ``col`` (int32[nnz]) and ``val`` (float64[nnz]) holding the strictly lower
-triangle L of S = L - L^T.
+triangle L of S = L - L^T (or, where ``symmetric=True`` is passed, of the
+symmetric S = L + L^T; a diagonal array D may join the scalar shift).
 """
 from __future__ import annotations
 
@@ -51,10 +52,13 @@ def _L():
             "or_validate": ([i64, i64, _vp, _vp], ctypes.c_int),
             "or_rcm": ([i32, _vp, _vp, _vp], ctypes.c_int),
             "or_permute": ([i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+            "or_permute_sign": ([i32, _vp, _vp, _vp, _vp, d, _vp, _vp, _vp], ctypes.c_int),
             "or_split": ([i32, _vp, _vp, i32, i32, _vp, _vp, _vp], ctypes.c_int),
             "or_full_csr": ([i32, _vp, _vp, _vp, d, _vp, _vp, _vp], i64),
+            "or_full_csr_ex": ([i32, _vp, _vp, _vp, d, _vp, d, _vp, _vp, _vp], i64),
             "or_csr_spmv": ([i32, _vp, _vp, _vp, _vp, _vp], None),
             "or_sss_spmv": ([i32, _vp, _vp, _vp, d, _vp, _vp], None),
+            "or_sss_spmv_ex": ([i32, _vp, _vp, _vp, d, _vp, d, _vp, _vp], None),
             "or_round_f32": ([i64, _vp, _vp], None),
             "or_round_bf16": ([i64, _vp, _vp], None),
             "or_bf16_to_f64": ([i64, _vp, _vp], None),
@@ -99,15 +103,18 @@ def rcm(L) -> np.ndarray:
     return perm
 
 
-def permute(L, perm) -> SimpleNamespace:
-    """Strictly lower triangle of P S P^T (sign rule of eq. (2)), rows sorted."""
+def permute(L, perm, symmetric: bool = False) -> SimpleNamespace:
+    """Strictly lower triangle of P S P^T, rows sorted.  An entry that crosses
+    the diagonal is stored transposed with its sign flipped for a
+    skew-symmetric S (eq. (2)), unchanged for a symmetric S."""
     n, rp, c, v = _arrs(L)
     perm = np.ascontiguousarray(perm, np.int32)
     nnz = c.shape[0]
     orow = np.zeros(n + 1, np.int32)
     ocol = np.zeros(nnz, np.int32)
     oval = np.zeros(nnz, np.float64)
-    if n > 0 and _L().or_permute(n, _p(rp), _p(c), _p(v), _p(perm), _p(orow), _p(ocol), _p(oval)) != 0:
+    if n > 0 and _L().or_permute_sign(n, _p(rp), _p(c), _p(v), _p(perm), 1.0 if symmetric else -1.0, _p(orow),
+                                      _p(ocol), _p(oval)) != 0:
         raise MemoryError("or_permute")
     return SimpleNamespace(n=n, rowptr=orow, col=ocol, val=oval, nnz=int(nnz))
 
@@ -123,14 +130,17 @@ def split(L, w_in: int = -1, t_out: int = -1):
     return part, cnt, tuple(int(t) for t in params)
 
 
-def full_csr(L, alpha: float = 0.0):
-    """Full CSR (frow, fcol, fval) of alpha*I + S, columns ascending."""
+def full_csr(L, alpha: float = 0.0, diag=None, symmetric: bool = False):
+    """Full CSR (frow, fcol, fval) of alpha*I + D + S, columns ascending;
+    S = L - L^T (skew, default) or L + L^T (symmetric); diag: D or None."""
     n, rp, c, v = _arrs(L)
     cap = 2 * c.shape[0] + n
     frow = np.zeros(n + 1, np.int32)
     fcol = np.zeros(max(cap, 1), np.int32)
     fval = np.zeros(max(cap, 1), np.float64)
-    m = _L().or_full_csr(n, _p(rp), _p(c), _p(v), float(alpha), _p(frow), _p(fcol), _p(fval))
+    d = None if diag is None else np.ascontiguousarray(diag, np.float64)
+    m = _L().or_full_csr_ex(n, _p(rp), _p(c), _p(v), float(alpha), _p(d) if d is not None else None,
+                            1.0 if symmetric else -1.0, _p(frow), _p(fcol), _p(fval))
     if m < 0:
         raise MemoryError("or_full_csr")
     return frow, fcol[:m].copy(), fval[:m].copy()
@@ -145,22 +155,28 @@ def csr_spmv(frow, fcol, fval, x) -> np.ndarray:
     return y
 
 
-def spmv(L, alpha: float, x) -> np.ndarray:
-    """y = (alpha*I + S) x by the full-CSR definition; x may be n or n x k."""
+def spmv(L, alpha: float, x, diag=None, symmetric: bool = False) -> np.ndarray:
+    """y = (alpha*I + D + S) x by the full-CSR definition; x may be n or n x k."""
     x = np.asarray(x, np.float64)
-    frow, fcol, fval = full_csr(L, alpha)
+    frow, fcol, fval = full_csr(L, alpha, diag, symmetric)
     if x.ndim == 1:
         return csr_spmv(frow, fcol, fval, x)
     return np.stack([csr_spmv(frow, fcol, fval, np.ascontiguousarray(x[:, j])) for j in range(x.shape[1])], 1)
 
 
-def sss_spmv(L, alpha: float, x) -> np.ndarray:
-    """Serial SSS skew product (the paper's baseline kernel semantics)."""
+def sss_spmv(L, alpha: float, x, diag=None, symmetric: bool = False) -> np.ndarray:
+    """Serial SSS product (the paper's baseline kernel semantics): skew by
+    default, symmetric on request, with an optional diagonal array."""
     n, rp, c, v = _arrs(L)
     x = np.ascontiguousarray(x, np.float64)
     y = np.zeros(n, np.float64)
     if n > 0:
-        _L().or_sss_spmv(n, _p(rp), _p(c), _p(v), float(alpha), _p(x), _p(y))
+        if diag is None and not symmetric:
+            _L().or_sss_spmv(n, _p(rp), _p(c), _p(v), float(alpha), _p(x), _p(y))
+        else:
+            d = None if diag is None else np.ascontiguousarray(diag, np.float64)
+            _L().or_sss_spmv_ex(n, _p(rp), _p(c), _p(v), float(alpha), _p(d) if d is not None else None,
+                                1.0 if symmetric else -1.0, _p(x), _p(y))
     return y
 
 

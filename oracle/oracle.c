@@ -11,7 +11,10 @@
  * S (S = -S^T, zero diagonal) in CSR: rowptr[n+1], col[nnz], val[nnz].  The
  * stored entry l_ij (i > j) stands for S_ij = l_ij and S_ji = -l_ij (the
  * symmetric-pair rule of eqs. (2)-(6), Section 3.1.2).  The system matrix is
- * A = alpha*I + S (shifted skew-symmetric form, Section 1).
+ * A = alpha*I + S (shifted skew-symmetric form, Section 1).  The "_ex" and
+ * "_sign" variants also cover the symmetric case (S_ji = +l_ij, the sign
+ * parameter tsign = +1) and a diagonal array D held beside the triangle as in
+ * SSS storage (Section 1), for A = alpha*I + D + S.
  *
  * Parity notes: every function here is pinned by the CPU tests against
  * closed forms, dense products, brute force or hand-derived cases.
@@ -216,6 +219,9 @@ typedef struct {
   int32_t c;
   double v;
 } cv_pair;
+int or_permute_sign(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                    const int32_t *perm, double tsign, int32_t *orow, int32_t *ocol, double *oval);
+
 static int cmp_cv(const void *a, const void *b) {
   int32_t x = ((const cv_pair *)a)->c, y = ((const cv_pair *)b)->c;
   return (x > y) - (x < y);
@@ -223,6 +229,13 @@ static int cmp_cv(const void *a, const void *b) {
 
 int or_permute(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
                const int32_t *perm, int32_t *orow, int32_t *ocol, double *oval) {
+  return or_permute_sign(n, rowptr, col, val, perm, -1.0, orow, ocol, oval);
+}
+
+/* The same with the sign of the transposed entry: tsign = -1 for a
+ * skew-symmetric matrix (A_ji = -A_ij), +1 for a symmetric one. */
+int or_permute_sign(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                    const int32_t *perm, double tsign, int32_t *orow, int32_t *ocol, double *oval) {
   if (n < 0) return 1;
   int32_t nnz = n > 0 ? rowptr[n] : 0;
   int32_t *iperm = (int32_t *)malloc((size_t)(n + 1) * sizeof(int32_t));
@@ -249,7 +262,7 @@ int or_permute(int32_t n, const int32_t *rowptr, const int32_t *col, const doubl
         tmp[fill[p]++].v = val[e];
       } else {
         tmp[fill[q]].c = p;
-        tmp[fill[q]++].v = -val[e];
+        tmp[fill[q]++].v = tsign * val[e];
       }
     }
   for (int32_t r = 0; r < n; r++) qsort(tmp + orow[r], (size_t)(orow[r + 1] - orow[r]), sizeof(cv_pair), cmp_cv);
@@ -294,11 +307,14 @@ int or_split(int32_t n, const int32_t *rowptr, const int32_t *col, int32_t w_in,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Full CSR of A = alpha*I + S with ascending columns in every row: row i holds
- * l_ij for stored (i, j), then alpha at (i, i) when alpha != 0, then -l_ki for
- * every stored (k, i), k > i.  frow[n+1]; fcol/fval sized 2*nnz + n. */
-int64_t or_full_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
-                    double alpha, int32_t *frow, int32_t *fcol, double *fval) {
+/* Full CSR of A = alpha*I + D + S with ascending columns in every row, for
+ * S = L + tsign L^T (tsign = -1: skew-symmetric, the paper's case; +1:
+ * symmetric).  Row i holds l_ij for stored (i, j), then alpha + d_i at (i, i)
+ * when that is nonzero (diag may be NULL: D = 0), then tsign l_ki for every
+ * stored (k, i), k > i.  frow[n+1]; fcol/fval sized 2*nnz + n. */
+int64_t or_full_csr_ex(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                       double alpha, const double *diag, double tsign, int32_t *frow, int32_t *fcol,
+                       double *fval) {
   int32_t *cnt = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
   int32_t *fill = (int32_t *)malloc((size_t)(n + 1) * sizeof(int32_t));
   if (!cnt || !fill) {
@@ -311,16 +327,20 @@ int64_t or_full_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const 
       cnt[col[e]]++;
     }
   frow[0] = 0;
-  for (int32_t i = 0; i < n; i++) frow[i + 1] = frow[i] + cnt[i] + (alpha != 0.0 ? 1 : 0);
+  for (int32_t i = 0; i < n; i++) {
+    double a = alpha + (diag ? diag[i] : 0.0);
+    frow[i + 1] = frow[i] + cnt[i] + (a != 0.0 ? 1 : 0);
+  }
   for (int32_t i = 0; i < n; i++) {
     int32_t f = frow[i];
     for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
       fcol[f] = col[e];
       fval[f++] = val[e];
     }
-    if (alpha != 0.0) {
+    double a = alpha + (diag ? diag[i] : 0.0);
+    if (a != 0.0) {
       fcol[f] = i;
-      fval[f++] = alpha;
+      fval[f++] = a;
     }
     fill[i] = f;
   }
@@ -328,11 +348,17 @@ int64_t or_full_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const 
     for (int32_t e = rowptr[k]; e < rowptr[k + 1]; e++) {
       int32_t i = col[e];
       fcol[fill[i]] = k;
-      fval[fill[i]++] = -val[e];
+      fval[fill[i]++] = tsign * val[e];
     }
   int64_t total = frow[n];
   free(cnt); free(fill);
   return total;
+}
+
+/* Full CSR of A = alpha*I + S, S skew-symmetric. */
+int64_t or_full_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                    double alpha, int32_t *frow, int32_t *fcol, double *fval) {
+  return or_full_csr_ex(n, rowptr, col, val, alpha, NULL, -1.0, frow, fcol, fval);
 }
 
 /* y_i = sum_j a_ij x_j over row i in ascending column order. */
@@ -357,6 +383,22 @@ void or_sss_spmv(int32_t n, const int32_t *rowptr, const int32_t *col, const dou
       double l = val[e];
       y[i] += l * x[j];
       y[j] -= l * x[i];
+    }
+}
+
+/* The serial SSS product with the diagonal array of SSS storage (Section 1)
+ * and the sign of the transposed update: y = alpha*x + d .* x (diag may be
+ * NULL); then y_i += l * x_j and y_j += tsign * l * x_i per stored l_ij
+ * (tsign = -1 skew-symmetric, +1 symmetric). */
+void or_sss_spmv_ex(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                    double alpha, const double *diag, double tsign, const double *x, double *y) {
+  for (int32_t i = 0; i < n; i++) y[i] = alpha * x[i] + (diag ? diag[i] * x[i] : 0.0);
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+      int32_t j = col[e];
+      double l = val[e];
+      y[i] += l * x[j];
+      y[j] += tsign * l * x[i];
     }
 }
 
