@@ -51,6 +51,11 @@ typedef enum { PARS3_F64 = 0, PARS3_F32 = 1, PARS3_BF16 = 2 } pars3_dtype;
 
 enum { PARS3_ORDER_RCM = 0, PARS3_ORDER_ORIGINAL = 1 };
 
+/* What the stored triangle L stands for: S = L - L^T (skew-symmetric, the
+ * paper's case) or S = L + L^T (symmetric: the SSS format the paper starts
+ * from, Section 1, where the same one-triangle storage serves both). */
+typedef enum { PARS3_SKEW = 0, PARS3_SYMMETRIC = 1 } pars3_kind;
+
 typedef struct pars3_matrix pars3_matrix;
 
 /* Split and layout parameters of pars3_reorder (Sections 1 and 3.1.2: the
@@ -107,6 +112,27 @@ pars3_status pars3_validate(int64_t n, int64_t nnz_lower, const int32_t *rowptr,
 pars3_status pars3_create(int64_t n, int64_t nnz_lower, const int32_t *rowptr, const int32_t *col,
                           const double *val, pars3_matrix **out);
 
+/* SSS storage (Section 1): the strictly lower triangle as for pars3_create,
+ * plus an optional diagonal array diag[n] (host, FP64; NULL: D = 0), and the
+ * kind of S.  Products then compute y = shift*x + D x + S x with
+ * S = L - L^T (PARS3_SKEW) or L + L^T (PARS3_SYMMETRIC).  A skew matrix
+ * without a diagonal is exactly what pars3_create makes.  The diagonal is
+ * copied to the device (FP64, and rounded to FP32 for FP32 vectors) and
+ * follows the reordering.  The MRS solvers need S skew-symmetric and D = 0
+ * (ESTATE otherwise).  Errors: those of pars3_create; EINVAL for another
+ * kind. */
+pars3_status pars3_create_sss(int64_t n, int64_t nnz_lower, const int32_t *rowptr, const int32_t *col,
+                              const double *val, const double *diag, int32_t kind, pars3_matrix **out);
+
+/* *kind receives the handle's pars3_kind, *has_diag 1 when a diagonal array
+ * was given (either pointer may be NULL). */
+pars3_status pars3_get_kind(const pars3_matrix *A, int32_t *kind, int32_t *has_diag);
+
+/* The diagonal array in the reordered numbering (host, n doubles:
+ * out[k] = diag[perm[k]]).  ESTATE before pars3_reorder or without a
+ * diagonal.  Synchronous. */
+pars3_status pars3_get_diagonal(const pars3_matrix *A, double *out);
+
 /* Frees every device and host resource of the handle.  NULL is allowed. */
 void pars3_destroy(pars3_matrix *A);
 
@@ -119,7 +145,9 @@ void pars3_destroy(pars3_matrix *A);
 pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *p, void *stream);
 
 /* y = shift*x + S*x  (the shifted skew-symmetric product; Section 1 and eqs.
- * (2)-(6)).  x and y are device arrays of n x k values, row-major (k values of
+ * (2)-(6)); for a handle from pars3_create_sss, y = shift*x + D x + S x with
+ * S of the handle's kind (a symmetric S adds the transposed products instead
+ * of subtracting them).  x and y are device arrays of n x k values, row-major (k values of
  * one row are contiguous), k in {1, 2, 4, 8}.  vec_dtype is PARS3_F64 when the
  * stored values are FP64 and PARS3_F32 when they are FP32 or BF16 (products
  * formed in FP32, summed per row in FP64, results rounded to FP32).  order = PARS3_ORDER_RCM: x and y are in the reordered
@@ -160,7 +188,9 @@ pars3_status pars3_get_profile(pars3_matrix *A, pars3_profile *out);
 
 /* Full-CSR comparison path (the storage that keeps every nonzero, Section 1).
  * pars3_csr_create builds, on the GPU, the full CSR of S (both triangles,
- * 2*nnz entries, columns ascending in every row) in the reordered numbering
+ * 2*nnz entries, columns ascending in every row; with a diagonal array, D + S
+ * with an entry d_i at (i, i) for every nonzero d_i, and the transposed
+ * entries signed by the handle's kind) in the reordered numbering
  * (order = PARS3_ORDER_RCM, after pars3_reorder) or in the caller's numbering
  * (PARS3_ORDER_ORIGINAL), with FP64 or FP32 values (value_dtype).  Synchronous.
  * pars3_csr_spmv computes y = shift*x + S*x (device vectors of n values of the
@@ -168,8 +198,10 @@ pars3_status pars3_get_profile(pars3_matrix *A, pars3_profile *out);
  * (a power-of-two group of lanes per row) or engine 1 = rocSPARSE's CSR
  * product (default algorithm; shift must be 0 there).  Asynchronous.
  * pars3_csr_get copies the CSR (FP64 values) to caller-allocated host arrays
- * rowptr[n+1], col[2*nnz], val[2*nnz]; NULL outputs are skipped. */
+ * rowptr[n+1], col[m], val[m] (m from pars3_csr_size: 2*nnz plus the nonzero
+ * diagonal entries); NULL outputs are skipped. */
 typedef struct pars3_csr pars3_csr;
+pars3_status pars3_csr_size(const pars3_csr *C, int64_t *n, int64_t *nnz_full);
 pars3_status pars3_csr_create(const pars3_matrix *A, int32_t order, int32_t value_dtype, pars3_csr **out);
 pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x, void *y, int32_t engine, void *stream);
 pars3_status pars3_csr_get(const pars3_csr *C, int32_t *rowptr, int32_t *col, double *val);
@@ -268,6 +300,9 @@ typedef struct {
   double time_ms;      /* wall time of the call */
 } pars3_mrs_info;
 
+/* The solver needs A = alpha*I + S with S skew-symmetric: a handle made by
+ * pars3_create_sss with PARS3_SYMMETRIC or with a diagonal array gives
+ * ESTATE. */
 void pars3_mrs_opts_default(pars3_mrs_opts *o);
 pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, double *x, const pars3_mrs_opts *opts,
                              pars3_mrs_info *info, void *stream);
@@ -282,7 +317,8 @@ pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, dou
  *    they must outlive it and must not be re-split while it exists).
  *  pars3_batch_info: number of items, persistent grid size and the 9 queue
  *    boundaries (host outputs, each may be NULL).
- *  pars3_batch_spmv: y_i = shifts[i] x_i + S_i x_i for every matrix i, with
+ *  pars3_batch_spmv: y_i = shifts[i] x_i + D_i x_i + S_i x_i for every matrix
+ *    i (D_i = 0 and S_i skew unless made by pars3_create_sss), with
  *    host arrays x[m], y[m] of device pointers (n_i x k row-major vectors in
  *    matrix i's reordered numbering, k in {1, 2, 4, 8}); shifts (host, m) may
  *    be NULL (all zero); 16-byte aligned when k > 1; vec_dtype and
@@ -293,9 +329,12 @@ pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, dou
  *  pars3_batch_mrs_solve: MRS for (alphas[i] I + S_i) x_i = b_i for every i
  *    (host arrays of m device pointers to FP64 vectors; x holds x0 on entry),
  *    FP64 iterations (opts->precision must be PARS3_F64; FP64 values
- *    needed), all systems advanced together by one persistent product, one
- *    scalar kernel and one vector kernel per iteration (systems that have
- *    converged are skipped), two iterations per graph replay.  infos (host, m,
+ *    needed), all systems advanced together by one persistent product per
+ *    iteration (the previous iteration's vector update fused into it) and one
+ *    scalar kernel (systems that have converged are skipped), six iterations
+ *    per graph replay, the work list compacted whenever the number of running
+ *    systems halves (ESTATE if a matrix is symmetric or has a diagonal
+ *    array).  infos (host, m,
  *    may be NULL) per system; time_ms is the whole batch's.  Returns the worst
  *    status (ENOCONV, EBREAKDOWN, ENAN) if any system fails.  Synchronous. */
 typedef struct pars3_batch pars3_batch;

@@ -26,6 +26,7 @@ STATUS_NAMES = ["OK", "EINVAL", "ENOTLOWER", "EUNSORTED", "ENOMEM", "EHIP", "EST
 # pars3_dtype
 F64, F32, BF16 = 0, 1, 2
 ORDER_RCM, ORDER_ORIGINAL = 0, 1
+SKEW, SYMMETRIC = 0, 1
 
 
 class Pars3Unavailable(RuntimeError):
@@ -89,6 +90,9 @@ SIGNATURES = {
     "pars3_split_params_default": ([ctypes.POINTER(SplitParams)], None),
     "pars3_validate": ([_i64, _i64, _vp, _vp], _st),
     "pars3_create": ([_i64, _i64, _vp, _vp, _vp, ctypes.POINTER(_vp)], _st),
+    "pars3_create_sss": ([_i64, _i64, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_vp)], _st),
+    "pars3_get_kind": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)], _st),
+    "pars3_get_diagonal": ([_vp, _vp], _st),
     "pars3_destroy": ([_vp], None),
     "pars3_reorder": ([_vp, ctypes.POINTER(SplitParams), _vp], _st),
     "pars3_spmv": ([_vp, _d, _vp, _vp, _i32, _i32, _i32, _vp], _st),
@@ -101,6 +105,7 @@ SIGNATURES = {
     "pars3_csr_create": ([_vp, _i32, _i32, ctypes.POINTER(_vp)], _st),
     "pars3_csr_spmv": ([_vp, _d, _vp, _vp, _i32, _vp], _st),
     "pars3_csr_get": ([_vp, _vp, _vp, _vp], _st),
+    "pars3_csr_size": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _st),
     "pars3_csr_destroy": ([_vp], None),
     "pars3_features": ([_vp, _vp], _st),
     "pars3_tune_grid_default": ([_i32, _vp, _i32, ctypes.POINTER(_i32)], _st),
@@ -211,6 +216,32 @@ def pars3_create(n, nnz, rowptr, col, val):
     return h
 
 
+def pars3_create_sss(n, nnz, rowptr, col, val, diag=None, kind=SKEW):
+    rp = np.ascontiguousarray(rowptr, np.int32)
+    c = np.ascontiguousarray(col, np.int32)
+    v = np.ascontiguousarray(val, np.float64)
+    d = None if diag is None else np.ascontiguousarray(diag, np.float64)
+    if d is not None and d.shape != (n,):
+        raise ValueError("diag must hold n values")
+    h = _vp()
+    dp = None if d is None else d.ctypes.data  # numpy gives empty arrays an address too
+    _check(lib().pars3_create_sss(n, nnz, _ptr(rp), _ptr(c), _ptr(v), dp, int(kind), ctypes.byref(h)),
+           "pars3_create_sss")
+    return h
+
+
+def pars3_get_kind(h):
+    k, d = _i32(), _i32()
+    _check(lib().pars3_get_kind(h, ctypes.byref(k), ctypes.byref(d)), "pars3_get_kind")
+    return int(k.value), bool(d.value)
+
+
+def pars3_get_diagonal(h, n):
+    out = np.zeros(max(n, 1), np.float64)
+    _check(lib().pars3_get_diagonal(h, _ptr(out)), "pars3_get_diagonal")
+    return out[:n]
+
+
 def pars3_destroy(h):
     if h:
         lib().pars3_destroy(h)
@@ -274,7 +305,15 @@ def pars3_csr_spmv(c, shift, x, y, engine=0, stream=None):
     _check(lib().pars3_csr_spmv(c, float(shift), _ptr(x), _ptr(y), int(engine), _stream(stream)), "pars3_csr_spmv")
 
 
-def pars3_csr_get(c, n, nnz_full):
+def pars3_csr_size(c):
+    n, m = _i64(), _i64()
+    _check(lib().pars3_csr_size(c, ctypes.byref(n), ctypes.byref(m)), "pars3_csr_size")
+    return int(n.value), int(m.value)
+
+
+def pars3_csr_get(c, n=None, nnz_full=None):
+    if n is None or nnz_full is None:
+        n, nnz_full = pars3_csr_size(c)
     rp = np.zeros(n + 1, np.int32)
     col = np.zeros(nnz_full, np.int32)
     val = np.zeros(nnz_full, np.float64)
@@ -498,10 +537,14 @@ class Matrix:
     """Owning wrapper of a ``pars3_matrix`` handle built from a strictly lower
     CSR (any object with n, rowptr, col, val)."""
 
-    def __init__(self, L):
+    def __init__(self, L, diag=None, symmetric=False):
         self.n = int(L.n)
         self.nnz = int(len(L.col))
-        self.h = pars3_create(self.n, self.nnz, L.rowptr, L.col, L.val)
+        self.kind = SYMMETRIC if symmetric else SKEW
+        if diag is None and not symmetric:
+            self.h = pars3_create(self.n, self.nnz, L.rowptr, L.col, L.val)
+        else:
+            self.h = pars3_create_sss(self.n, self.nnz, L.rowptr, L.col, L.val, diag, self.kind)
 
     def close(self):
         if self.h:
@@ -542,6 +585,10 @@ class Matrix:
 
     def features(self):
         return pars3_features(self.h)
+
+    def diagonal(self):
+        """The diagonal array in the reordered numbering."""
+        return pars3_get_diagonal(self.h, self.n)
 
     def perm(self):
         return pars3_get_perm(self.h, self.n)

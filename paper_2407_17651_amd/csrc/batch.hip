@@ -346,8 +346,11 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   if (o.precision != PARS3_F64) return fail(PARS3_EINVAL, "batch mrs: only FP64 iterations are batched");
   if (o.order != PARS3_ORDER_RCM && o.order != PARS3_ORDER_ORIGINAL) return fail(PARS3_EINVAL, "batch mrs: bad order");
   const int32_t m = (int32_t)B->mats.size();
-  for (int32_t i = 0; i < m; i++)
+  for (int32_t i = 0; i < m; i++) {
     if (B->mats[i]->n > 0 && (!b[i] || !x[i])) return fail(PARS3_EINVAL, "batch mrs: NULL vector of system %d", i);
+    if (B->mats[i]->kind != PARS3_SKEW || B->mats[i]->diag.p)
+      return fail(PARS3_ESTATE, "batch mrs: system %d is not alpha*I + S with S skew-symmetric", i);
+  }
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t cs = (hipStream_t)stream;
   hipStream_t s = B->gs;

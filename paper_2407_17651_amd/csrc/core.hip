@@ -40,8 +40,14 @@ extern "C" pars3_status pars3_validate(int64_t n, int64_t nnz, const int32_t *ro
 
 extern "C" pars3_status pars3_create(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
                                      const double *val, pars3_matrix **out) {
+  return pars3_create_sss(n, nnz, rowptr, col, val, nullptr, PARS3_SKEW, out);
+}
+
+extern "C" pars3_status pars3_create_sss(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                                         const double *val, const double *diag, int32_t kind, pars3_matrix **out) {
   if (!out) return fail(PARS3_EINVAL, "create: out is NULL");
   *out = nullptr;
+  if (kind != PARS3_SKEW && kind != PARS3_SYMMETRIC) return fail(PARS3_EINVAL, "create: bad kind %d", kind);
   pars3_status st = pars3_validate(n, nnz, rowptr, col);
   if (st != PARS3_OK) return st;
   if (nnz > 0 && !val) return fail(PARS3_EINVAL, "create: val is NULL");
@@ -62,7 +68,29 @@ extern "C" pars3_status pars3_create(int64_t n, int64_t nnz, const int32_t *rowp
       (nnz > 0 && (e = hipMemcpy(A->col.p, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) ||
       (nnz > 0 && (e = hipMemcpy(A->val.p, val, nnz * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess))
     return bail(fail(PARS3_EHIP, "create: copy to device failed: %s", hipGetErrorString(e)));
+  A->kind = kind;
+  if (diag) {
+    if ((e = A->diag.alloc(n)) != hipSuccess)
+      return bail(fail(PARS3_ENOMEM, "create: device allocation failed: %s", hipGetErrorString(e)));
+    if (n > 0 && (e = hipMemcpy(A->diag.p, diag, n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+      return bail(fail(PARS3_EHIP, "create: copy to device failed: %s", hipGetErrorString(e)));
+  }
   *out = A;
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_get_kind(const pars3_matrix *A, int32_t *kind, int32_t *has_diag) {
+  if (!A) return fail(PARS3_EINVAL, "get_kind: NULL handle");
+  if (kind) *kind = A->kind;
+  if (has_diag) *has_diag = A->diag.p ? 1 : 0;
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_get_diagonal(const pars3_matrix *A, double *out) {
+  if (!A || !out) return fail(PARS3_EINVAL, "get_diagonal: NULL argument");
+  if (!A->perm_done) return fail(PARS3_ESTATE, "get_diagonal: call pars3_reorder first");
+  if (!A->diag.p) return fail(PARS3_ESTATE, "get_diagonal: the handle has no diagonal array");
+  if (A->n) P3_HIP(hipMemcpy(out, A->pdiag.p, A->n * sizeof(double), hipMemcpyDeviceToHost));
   return PARS3_OK;
 }
 
@@ -126,6 +154,7 @@ extern "C" pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params 
     if (p.permute) P3_TRY(p3::rcm_gpu(A, s));
     else P3_TRY(p3::identity_perm_gpu(A, s));
     P3_TRY(p3::permute_gpu(A, s));
+    if (A->diag.p) P3_TRY(p3::permute_diagonal(A, s));
     A->perm_done = true;
     A->perm_kind = p.permute;
   }

@@ -2,6 +2,8 @@
 // CSR form (the storage that keeps every nonzero, Section 1), multiplied by a
 // plain CSR-vector kernel or by rocSPARSE.  It is the baseline the skew
 // product is measured against; it reads every matrix value twice as often.
+// A diagonal array adds an entry d_i at (i, i) for every nonzero d_i; the
+// transposed entries are -l (skew) or +l (symmetric).
 #include <algorithm>
 
 #include <rocsparse/rocsparse.h>
@@ -30,18 +32,25 @@ namespace p3 {
 static constexpr int TB = 256;
 static inline unsigned nblk(int64_t m) { return (unsigned)std::max<int64_t>(1, cdiv(m, TB)); }
 
-__global__ void k_full_count(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t n,
-                             int32_t *__restrict__ cnt) {
+// entries of row i up to and including its diagonal one
+__device__ __forceinline__ int32_t lower_len(const int32_t *__restrict__ rp, const double *__restrict__ dg,
+                                             int32_t i) {
+  return rp[i + 1] - rp[i] + (dg && dg[i] != 0.0 ? 1 : 0);
+}
+__global__ void k_full_count(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                             const double *__restrict__ dg, int32_t n, int32_t *__restrict__ cnt) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  atomicAdd(&cnt[i], rp[i + 1] - rp[i]);
+  atomicAdd(&cnt[i], lower_len(rp, dg, i));
   for (int32_t e = rp[i]; e < rp[i + 1]; e++) atomicAdd(&cnt[col[e]], 1);
 }
-// row i: its lower entries in place (ascending), then -l_ki for every stored
-// (k, i), k > i, in arbitrary order (sorted by k_full_sort_upper)
+// row i: its lower entries in place (ascending), d_i when nonzero, then
+// tsign l_ki for every stored (k, i), k > i, in arbitrary order (sorted by
+// k_full_sort_upper)
 __global__ void k_full_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                            const double *__restrict__ val, int32_t n, const int32_t *__restrict__ frow,
-                            int32_t *__restrict__ ufill, int32_t *__restrict__ fcol, double *__restrict__ fval) {
+                            const double *__restrict__ val, const double *__restrict__ dg, double tsign, int32_t n,
+                            const int32_t *__restrict__ frow, int32_t *__restrict__ ufill, int32_t *__restrict__ fcol,
+                            double *__restrict__ fval) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int32_t f = frow[i];
@@ -50,9 +59,13 @@ __global__ void k_full_fill(const int32_t *__restrict__ rp, const int32_t *__res
     fcol[f] = j;
     fval[f++] = val[e];
     const int32_t slot = atomicAdd(&ufill[j], 1);
-    const int32_t at = frow[j] + (rp[j + 1] - rp[j]) + slot;
+    const int32_t at = frow[j] + lower_len(rp, dg, j) + slot;
     fcol[at] = i;
-    fval[at] = -val[e];
+    fval[at] = tsign * val[e];
+  }
+  if (dg && dg[i] != 0.0) {
+    fcol[f] = i;
+    fval[f] = dg[i];
   }
 }
 __device__ __forceinline__ int32_t row_of_csr(const int32_t *__restrict__ ptr, int32_t n, int64_t e) {
@@ -65,13 +78,14 @@ __device__ __forceinline__ int32_t row_of_csr(const int32_t *__restrict__ ptr, i
   return lo;
 }
 // rank sort of the upper part of every row by column (columns are distinct)
-__global__ void k_full_sort_upper(const int32_t *__restrict__ rp, const int32_t *__restrict__ frow, int32_t n,
-                                  int64_t m, const int32_t *__restrict__ fcol_in, const double *__restrict__ fval_in,
+__global__ void k_full_sort_upper(const int32_t *__restrict__ rp, const double *__restrict__ dg,
+                                  const int32_t *__restrict__ frow, int32_t n, int64_t m,
+                                  const int32_t *__restrict__ fcol_in, const double *__restrict__ fval_in,
                                   int32_t *__restrict__ fcol, double *__restrict__ fval) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m) return;
   const int32_t r = row_of_csr(frow, n, e);
-  const int32_t ub = frow[r] + (rp[r + 1] - rp[r]);
+  const int32_t ub = frow[r] + lower_len(rp, dg, r);
   if (e < ub) {
     fcol[e] = fcol_in[e];
     fval[e] = fval_in[e];
@@ -145,35 +159,41 @@ extern "C" pars3_status pars3_csr_create(const pars3_matrix *A, int32_t order, i
   if (!C) return fail(PARS3_ENOMEM, "csr_create: host allocation failed");
   auto run = [&]() -> pars3_status {
     const int32_t n = (int32_t)A->n;
-    const int64_t m = 2 * A->nnz;
     C->n = n;
-    C->nnz = m;
     C->order = order;
     C->vdtype = value_dtype;
     const int32_t *rp = order == PARS3_ORDER_RCM ? A->prow.p : A->rowptr.p;
     const int32_t *cl = order == PARS3_ORDER_RCM ? A->pcol.p : A->col.p;
     const double *vl = order == PARS3_ORDER_RCM ? A->pval.p : A->val.p;
+    const double *dg = order == PARS3_ORDER_RCM ? A->pdiag.p : A->diag.p;
+    const double tsign = A->kind == PARS3_SYMMETRIC ? 1.0 : -1.0;
     hipStream_t s = nullptr;
     p3::dbuf<int32_t> cnt, ufill, fcol0;
     p3::dbuf<double> fval0;
     P3_HIP(C->rowptr.alloc(n + 1));
-    P3_HIP(C->col.alloc(m));
-    P3_HIP(C->v64.alloc(m));
     P3_HIP(cnt.alloc(n));
     P3_HIP(ufill.alloc(n));
-    P3_HIP(fcol0.alloc(m));
-    P3_HIP(fval0.alloc(m));
     if (n > 0) {
       P3_HIP(hipMemsetAsync(cnt.p, 0, n * sizeof(int32_t), s));
       P3_HIP(hipMemsetAsync(ufill.p, 0, n * sizeof(int32_t), s));
-      p3::k_full_count<<<p3::nblk(n), p3::TB, 0, s>>>(rp, cl, n, cnt.p);
+      p3::k_full_count<<<p3::nblk(n), p3::TB, 0, s>>>(rp, cl, dg, n, cnt.p);
       P3_LAUNCHED();
     }
     P3_TRY(p3::scan_i32(cnt.p, C->rowptr.p, n, s));
+    int32_t total = 0;
+    P3_HIP(hipMemcpyAsync(&total, C->rowptr.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P3_HIP(hipStreamSynchronize(s));
+    const int64_t m = total;
+    C->nnz = m;
+    P3_HIP(C->col.alloc(m));
+    P3_HIP(C->v64.alloc(m));
+    P3_HIP(fcol0.alloc(m));
+    P3_HIP(fval0.alloc(m));
     if (m > 0) {
-      p3::k_full_fill<<<p3::nblk(n), p3::TB, 0, s>>>(rp, cl, vl, n, C->rowptr.p, ufill.p, fcol0.p, fval0.p);
+      p3::k_full_fill<<<p3::nblk(n), p3::TB, 0, s>>>(rp, cl, vl, dg, tsign, n, C->rowptr.p, ufill.p, fcol0.p,
+                                                      fval0.p);
       P3_LAUNCHED();
-      p3::k_full_sort_upper<<<p3::nblk(m), p3::TB, 0, s>>>(rp, C->rowptr.p, n, m, fcol0.p, fval0.p, C->col.p,
+      p3::k_full_sort_upper<<<p3::nblk(m), p3::TB, 0, s>>>(rp, dg, C->rowptr.p, n, m, fcol0.p, fval0.p, C->col.p,
                                                             C->v64.p);
       P3_LAUNCHED();
     }
@@ -262,6 +282,13 @@ extern "C" pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x
   rocsparse_destroy_dnvec_descr(dx);
   rocsparse_destroy_dnvec_descr(dy);
   if (r != rocsparse_status_success) return fail(PARS3_EHIP, "csr_spmv: rocsparse_spmv failed (%d)", (int)r);
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_csr_size(const pars3_csr *C, int64_t *n, int64_t *nnz_full) {
+  if (!C) return fail(PARS3_EINVAL, "csr_size: NULL handle");
+  if (n) *n = C->n;
+  if (nnz_full) *nnz_full = C->nnz;
   return PARS3_OK;
 }
 

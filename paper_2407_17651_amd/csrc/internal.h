@@ -187,9 +187,14 @@ void mrs_ws_free(mrs_ws *w);
 struct pars3_matrix {
   int64_t n = 0, nnz = 0;
   int device = 0;
-  // input, original numbering
+  // PARS3_SKEW (S = L - L^T) or PARS3_SYMMETRIC (S = L + L^T)
+  int32_t kind = PARS3_SKEW;
+  // input, original numbering; diag: the SSS diagonal array (empty: D = 0)
   p3::dbuf<int32_t> rowptr, col;
-  p3::dbuf<double> val;
+  p3::dbuf<double> val, diag;
+  // the diagonal in the reordered numbering, FP64 and rounded to FP32
+  p3::dbuf<double> pdiag;
+  p3::dbuf<float> pdiag32;
   // reordering
   bool perm_done = false;
   int32_t perm_kind = -1;  // 1 RCM, 0 identity
@@ -225,6 +230,8 @@ namespace p3 {
 pars3_status rcm_gpu(pars3_matrix *A, hipStream_t s);
 pars3_status identity_perm_gpu(pars3_matrix *A, hipStream_t s);
 pars3_status permute_gpu(pars3_matrix *A, hipStream_t s);
+// pdiag[k] = diag[perm[k]] and its FP32 rounding
+pars3_status permute_diagonal(pars3_matrix *A, hipStream_t s);
 // layout.hip
 pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipStream_t s);
 // spmv.hip
@@ -327,7 +334,9 @@ struct prod_task {
   const uint32_t *ent_rc;
   const void *ent_v, *dia;
   int32_t w_in, ntiles, lgT, n;
+  int32_t sym;       // 1: S = L + L^T (the transposed update keeps its sign)
   double shift;
+  const void *dg;    // diagonal array in the vector type, or nullptr (D = 0)
   const void *x;
   void *y;
   const void *z;

@@ -307,6 +307,8 @@ extern "C" pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const dou
   using namespace p3;
   if (!A) return fail(PARS3_EINVAL, "mrs: NULL handle");
   if (!A->split_done) return fail(PARS3_ESTATE, "mrs: call pars3_reorder first");
+  if (A->kind != PARS3_SKEW || A->diag.p)
+    return fail(PARS3_ESTATE, "mrs: the solver needs alpha*I + S with S skew-symmetric and no diagonal array");
   pars3_mrs_opts o;
   if (opts) o = *opts;
   else pars3_mrs_opts_default(&o);

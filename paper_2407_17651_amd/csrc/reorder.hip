@@ -545,17 +545,18 @@ pars3_status rcm_gpu(pars3_matrix *A, hipStream_t s) {
 
 // ------------------------------------------------------------ permutation
 // Entry (i, j, l), i > j, lands at (p, q) = (iperm[i], iperm[j]); it is stored
-// at (max, min) with value l if p > q and -l otherwise (S_ji = -S_ij, eq. (2)).
+// at (max, min) with value l if p > q and -l otherwise (S_ji = -S_ij, eq. (2));
+// a symmetric S keeps l either way.
 __global__ void k_perm_keys(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, int32_t n,
-                            int64_t nnz, const int32_t *__restrict__ iperm, int bits, uint64_t *__restrict__ keys,
-                            uint32_t *__restrict__ vals) {
+                            int64_t nnz, const int32_t *__restrict__ iperm, int bits, int sym,
+                            uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
   int32_t i = row_of(rowptr, n, e);  // the last row whose pointer is <= e owns e
   int32_t p = iperm[i], q = iperm[col[e]];
   uint64_t hi = (uint64_t)(p > q ? p : q), lo = (uint64_t)(p > q ? q : p);
   keys[e] = (hi << bits) | lo;
-  vals[e] = (uint32_t)e | (p > q ? 0u : 0x80000000u);
+  vals[e] = (uint32_t)e | (p > q || sym ? 0u : 0x80000000u);
 }
 __global__ void k_perm_fill(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t nnz, int bits,
                             const double *__restrict__ val, int32_t *__restrict__ pcol, double *__restrict__ pval,
@@ -595,12 +596,34 @@ pars3_status permute_gpu(pars3_matrix *A, hipStream_t s) {
   P3_HIP(v1.alloc(nnz));
   P3_HIP(rcnt.alloc(n));
   P3_HIP(hipMemsetAsync(rcnt.p, 0, n * sizeof(int32_t), s));
-  k_perm_keys<<<nblk(nnz), TB, 0, s>>>(A->rowptr.p, A->col.p, n, nnz, A->iperm.p, bits, k0.p, v0.p);
+  k_perm_keys<<<nblk(nnz), TB, 0, s>>>(A->rowptr.p, A->col.p, n, nnz, A->iperm.p, bits,
+                                       A->kind == PARS3_SYMMETRIC ? 1 : 0, k0.p, v0.p);
   P3_LAUNCHED();
   P3_TRY(radix_sort_pairs(k0.p, v0.p, k1.p, v1.p, nnz, 2 * bits, s));
   k_perm_fill<<<nblk(nnz), TB, 0, s>>>(k0.p, v0.p, nnz, bits, A->val.p, A->pcol.p, A->pval.p, rcnt.p);
   P3_LAUNCHED();
   P3_TRY(scan_i32(rcnt.p, A->prow.p, n, s));
+  P3_HIP(hipStreamSynchronize(s));
+  return PARS3_OK;
+}
+
+__global__ void k_perm_diag(const double *__restrict__ d, const int32_t *__restrict__ perm, int32_t n,
+                            double *__restrict__ pd, float *__restrict__ pd32) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double v = d[perm[k]];
+  pd[k] = v;
+  pd32[k] = (float)v;
+}
+
+pars3_status permute_diagonal(pars3_matrix *A, hipStream_t s) {
+  const int32_t n = (int32_t)A->n;
+  P3_HIP(A->pdiag.alloc(n));
+  P3_HIP(A->pdiag32.alloc(n));
+  if (n > 0) {
+    k_perm_diag<<<nblk(n), TB, 0, s>>>(A->diag.p, A->perm.p, n, A->pdiag.p, A->pdiag32.p);
+    P3_LAUNCHED();
+  }
   P3_HIP(hipStreamSynchronize(s));
   return PARS3_OK;
 }

@@ -1,6 +1,8 @@
 // Skew-symmetric product y = shift*x + S*x, S = L - L^T, from the stored
 // lower triangle only (eqs. (2)-(6), Section 3.1.2): every stored l_ij stands
-// for the pair y_i += l_ij x_j and y_j -= l_ij x_i.
+// for the pair y_i += l_ij x_j and y_j -= l_ij x_i.  The same kernels serve
+// the symmetric S = L + L^T of SSS storage (y_j += l_ij x_i) and its
+// diagonal array D (y_i += d_i x_i, Section 1), selected per launch.
 //
 // One launch, one workgroup per tile of T rows, no global atomics and one
 // plain store per output row.  The entries are stored once, grouped in
@@ -106,8 +108,9 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
 
 // Loads of one group of chunks (one per q) and their products added into
 // the LDS row sums; a descriptor with .y == CHUNK_EMPTY is skipped.
+// sym: the column side adds l_ij x_i (symmetric S) instead of subtracting it.
 template <class V, class X, int K>
-__device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT,
+__device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
                                             const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
                                             const X *__restrict__ x, double *ys) {
   int32_t slot[PRE], xrow[PRE];
@@ -137,7 +140,7 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
         const int32_t ri = (int32_t)(rc >> 16), cj = (int32_t)(rc & 0xffffu);
         slot[q] = col_side ? cj : ri;
         xrow[q] = (other << lgT) + (col_side ? ri : cj);
-        coef[q] = col_side ? -val : val;
+        coef[q] = col_side && !sym ? -val : val;
       }
     }
   }
@@ -158,8 +161,8 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
     }
 }
 
-// Output phase of a tile (after its LDS row sums are complete): y = shift x
-// + inner band + LDS sum (+ the solver epilogue), one store per row.
+// Output phase of a tile (after its LDS row sums are complete): y = (shift
+// + d_i) x + inner band + LDS sum (+ the solver epilogue), one store per row.
 template <class V, class X, int K, bool EP>
 __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const X (&xown)[K], const double *ys,
                                            double *s_red) {
@@ -167,8 +170,10 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
   const X *__restrict__ x = (const X *)a.x;
   X *__restrict__ y = (X *)a.y;
   const X *__restrict__ z = (const X *)a.z;
+  const X *__restrict__ dg = (const X *)a.dg;
   const int32_t n = a.n, w_in = a.w_in;
   const X shift = (X)a.shift;
+  const bool sym = a.sym != 0;
   const int32_t r0 = t << a.lgT;
   const int32_t rows = min(1 << a.lgT, n - r0);
   // fused solver iteration: scale of S x, and the pending vector update
@@ -204,15 +209,17 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
       if (i + k < n) {
         const X l = (X)vload<V>::nt(dia, bse + i + k);
         if (l != (X)0) {
+          const X lu = sym ? l : -l;  // S_i,i+k
 #pragma unroll
-          for (int c = 0; c < K; c++) acc[c] -= l * x[(i + k) * K + c];
+          for (int c = 0; c < K; c++) acc[c] += lu * x[(i + k) * K + c];
         }
       }
     }
+    const X sh = dg ? shift + dg[i] : shift;
 #pragma unroll
     for (int c = 0; c < K; c++) {
       const X xi = r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c];
-      acc[c] = EP ? shift * xi + sc * acc[c] : shift * xi + acc[c];
+      acc[c] = EP ? sh * xi + sc * acc[c] : sh * xi + acc[c];
     }
     if (EP && z) {
       const X zb = (X)*a.beta;
@@ -284,14 +291,14 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   }
   for (int32_t s = threadIdx.x; s < rows * KP<K>; s += TB) ys[s] = 0.0;
   __syncthreads();
-  chunk_group<V, X, K>(d, lane, lgT, a.ent_rc, ent_v, x, ys);
+  chunk_group<V, X, K>(d, lane, lgT, a.sym != 0, a.ent_rc, ent_v, x, ys);
   for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
 #pragma unroll
     for (int q = 0; q < PRE; q++) {
       const int32_t c = cb + q * (TB / 64);
       d[q] = c < o1 ? a.chunk_ovf[c] : make_uint2(0u, CHUNK_EMPTY);
     }
-    chunk_group<V, X, K>(d, lane, lgT, a.ent_rc, ent_v, x, ys);
+    chunk_group<V, X, K>(d, lane, lgT, a.sym != 0, a.ent_rc, ent_v, x, ys);
   }
   __syncthreads();
   tile_final<V, X, K, EP>(a, t, xown, ys, s_red);
@@ -365,6 +372,8 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   a.ntiles = L.ntiles;
   a.lgT = L.lgT;
   a.n = n;
+  a.sym = A->kind == PARS3_SYMMETRIC ? 1 : 0;
+  a.dg = sizeof(X) == 8 ? (const void *)A->pdiag.p : (const void *)A->pdiag32.p;
   a.shift = (double)shift;
   a.x = x;
   a.y = y;
@@ -498,6 +507,8 @@ pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, pr
   a->ntiles = L.ntiles;
   a->lgT = L.lgT;
   a->n = (int32_t)A->n;
+  a->sym = A->kind == PARS3_SYMMETRIC ? 1 : 0;
+  a->dg = vec_dtype == PARS3_F64 ? (const void *)A->pdiag.p : (const void *)A->pdiag32.p;
   if (vec_dtype == PARS3_F64) {
     if (!A->has_f64) return fail(PARS3_ESTATE, "batch: a matrix has no FP64 values");
     a->ent_v = L.ent_f64.p;
