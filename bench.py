@@ -32,7 +32,7 @@ SIZES = {"f64": (8, 8), "f32": (4, 4), "bf16": (2, 4)}  # (value bytes, vector b
 
 def kernel_name(dtype):
     v, x = {"f64": ("double", "double"), "f32": ("float", "float"), "bf16": ("unsigned short", "float")}[dtype]
-    return f"p3::k_tile_product<{v}, {x}, 1, false>"
+    return f"p3::k_tile_product<{v}, {x}, 1, false, false>"
 
 
 def source_hash():
@@ -158,6 +158,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-csr", action="store_true", help="skip the full-CSR comparison")
     ap.add_argument("--no-mrs", action="store_true", help="skip the MRS time-to-solution runs")
+    ap.add_argument("--no-sym", action="store_true", help="skip the symmetric-with-diagonal product")
     ap.add_argument("--mrs-reps", type=int, default=3, help="timed solves per MRS precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix workload")
     ap.add_argument("--warm-cache", action="store_true",
@@ -303,6 +304,33 @@ def main(argv=None):
                 p3.pars3_csr_destroy(c)
         best = min(v["ms"] for v in csr.values())
         out["full_csr"] = {"algorithmic_bytes": Bc, **csr, "best_ms": best, "skew_speedup_vs_best": round(best / ms, 3)}
+
+    # the symmetric variant with an SSS diagonal array on the same matrix and
+    # rotation: y = shift x + D x + (L + L^T) x; the diagonal adds n reads of
+    # the vector precision to the algorithmic bytes
+    if not args.no_sym:
+        dg = synth.values(n, 1203, "normal")
+        smats = [p3.Matrix(L, diag=dg, symmetric=True).reorder(value_dtype=vdt) for _ in range(copies)]
+
+        def sstep(s):
+            c = s % copies
+            p3.pars3_spmv(smats[c].h, shift, xs[c], ys[c], 1, vec, p3.ORDER_RCM)
+
+        for s in range(args.warmup):
+            sstep(s)
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for s in range(args.steps):
+            sstep(s)
+        s1.record()
+        torch.cuda.synchronize()
+        sms = s0.elapsed_time(s1) / args.steps
+        Bs = B + n * SIZES[args.dtype][1]
+        out["symmetric_diag"] = {"ms": round(sms, 5), "gbs": round(Bs / (sms * 1e-3) / 1e9, 2),
+                                 "algorithmic_bytes": Bs, "time_vs_skew": round(sms / ms, 3)}
+        del smats
+        torch.cuda.synchronize()
 
     # MRS time to an FP64 relative residual of 1e-10 on (0.5 I + S) x = A 1:
     # FP64-only against mixed precision (FP32 or BF16 inner solves, FP64

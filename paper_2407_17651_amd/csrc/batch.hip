@@ -316,7 +316,9 @@ extern "C" pars3_status pars3_batch_spmv(pars3_batch *B, const double *shifts, c
     P3_HIP(hipStreamSynchronize(s));
     P3_HIP(hipMemcpy(B->tasks.p, t.data(), m * sizeof(prod_task), hipMemcpyHostToDevice));
     P3_HIP(hipStreamBeginCapture(B->gs, hipStreamCaptureModeThreadLocal));
-    pars3_status st = launch_batch(vk, k, false, B->tasks.p, B->items.p, B->qbeg.p, B->grid, B->maxT, B->gs);
+    bool gen = false;
+    for (const pars3_matrix *A : B->mats) gen = gen || is_general(A);
+    pars3_status st = launch_batch(vk, k, false, gen, B->tasks.p, B->items.p, B->qbeg.p, B->grid, B->maxT, B->gs);
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(B->gs, &g);
     if (st != PARS3_OK) {
@@ -472,7 +474,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   k_bmrs_const<<<g1(m), BT, 0, s>>>(dev.p, m);
   k_bnorm<<<m, BT, 0, s>>>(Bv.p, doff.p, nb2.p);
   P3_LAUNCHED();
-  P3_TRY(launch_batch(PARS3_F64, 1, true, tk.p, ditems.p, dqb.p, grid, B->maxT, s));
+  P3_TRY(launch_batch(PARS3_F64, 1, true, false, tk.p, ditems.p, dqb.p, grid, B->maxT, s));
   k_bnorm<<<m, BT, 0, s>>>(Y.p, doff.p, nr2.p);
   k_bmrs_init<<<g1(m), BT, 0, s>>>(P, nb2.p, nr2.p, alph.p, o.tol, o.maxit, m);
   if (nvb) k_bmrs_start<<<nvb, BT, 0, s>>>(P);
@@ -489,7 +491,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
     P3_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     pars3_status st2 = PARS3_OK;
     for (int J = 1; J <= 6 && st2 == PARS3_OK; J++) {
-      st2 = launch_batch(PARS3_F64, 1, true, tk.p + (size_t)J * m, ditems.p, dqb.p, grid, B->maxT, s);
+      st2 = launch_batch(PARS3_F64, 1, true, false, tk.p + (size_t)J * m, ditems.p, dqb.p, grid, B->maxT, s);
       if (st2 == PARS3_OK) k_bmrs_scalar<<<m, 1024, 0, s>>>(P, (J - 1) & 1);
     }
     const hipError_t ee = hipStreamEndCapture(s, &graph);
@@ -546,7 +548,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   grid = persistent_grid((int64_t)hit.size());
   if (!hit.empty()) P3_HIP(hipMemcpyAsync(ditems.p, hit.data(), hit.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   P3_HIP(hipMemcpyAsync(dqb.p, hqb.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  P3_TRY(launch_batch(PARS3_F64, 1, true, tk.p, ditems.p, dqb.p, grid, B->maxT, s));
+  P3_TRY(launch_batch(PARS3_F64, 1, true, false, tk.p, ditems.p, dqb.p, grid, B->maxT, s));
   k_bnorm<<<m, BT, 0, s>>>(Y.p, doff.p, nr2.p);
   P3_LAUNCHED();
   std::vector<double> hr(m), hb(m);

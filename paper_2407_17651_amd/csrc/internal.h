@@ -357,8 +357,11 @@ pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, pr
 // Persistent product over many tasks: items (task, tile) in 8 queues
 // [qbeg[q], qbeg[q+1]), one per XCD, taken round-robin.  maxT: the largest
 // tile height among the tasks.  ep: with the solver epilogue (k = 1 only).
-pars3_status launch_batch(int vkind, int k, bool ep, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
-                          int32_t grid, int32_t maxT, hipStream_t s);
+// gen: some task is symmetric or has a diagonal array.
+pars3_status launch_batch(int vkind, int k, bool ep, bool gen, const prod_task *tasks, const int2 *items,
+                          const int32_t *qbeg, int32_t grid, int32_t maxT, hipStream_t s);
+// A symmetric matrix or one with a diagonal array (the general kernels).
+inline bool is_general(const pars3_matrix *A) { return A->kind != PARS3_SKEW || A->diag.p != nullptr; }
 // Product with an optional epilogue; value_dtype selects FP32 or BF16 values
 // when both are stored (-1: whichever is stored).
 pars3_status spmv_ex(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, int value_dtype,

@@ -163,17 +163,17 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
 
 // Output phase of a tile (after its LDS row sums are complete): y = (shift
 // + d_i) x + inner band + LDS sum (+ the solver epilogue), one store per row.
-template <class V, class X, int K, bool EP>
+template <class V, class X, int K, bool EP, bool GEN>
 __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const X (&xown)[K], const double *ys,
                                            double *s_red) {
   const V *__restrict__ dia = (const V *)a.dia;
   const X *__restrict__ x = (const X *)a.x;
   X *__restrict__ y = (X *)a.y;
   const X *__restrict__ z = (const X *)a.z;
-  const X *__restrict__ dg = (const X *)a.dg;
+  const X *__restrict__ dg = GEN ? (const X *)a.dg : nullptr;
   const int32_t n = a.n, w_in = a.w_in;
   const X shift = (X)a.shift;
-  const bool sym = a.sym != 0;
+  const bool sym = GEN && a.sym != 0;
   const int32_t r0 = t << a.lgT;
   const int32_t rows = min(1 << a.lgT, n - r0);
   // fused solver iteration: scale of S x, and the pending vector update
@@ -262,7 +262,9 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
 // (products are formed in the vector precision); LDS adds of FP64 measured
 // faster than of FP32 here.  Called by every thread of the workgroup.  EP:
 // the solver epilogue (y += beta z, per-tile sums of y^2) is compiled in.
-template <class V, class X, int K, bool EP>
+// GEN: the task's kind (symmetric or skew) and diagonal array are honoured;
+// without it the product is the skew one with the scalar shift only.
+template <class V, class X, int K, bool EP, bool GEN>
 __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double *ys, double *s_red) {
   const V *__restrict__ ent_v = (const V *)a.ent_v;
   const V *__restrict__ dia = (const V *)a.dia;
@@ -291,22 +293,23 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   }
   for (int32_t s = threadIdx.x; s < rows * KP<K>; s += TB) ys[s] = 0.0;
   __syncthreads();
-  chunk_group<V, X, K>(d, lane, lgT, a.sym != 0, a.ent_rc, ent_v, x, ys);
+  chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, a.ent_rc, ent_v, x, ys);
   for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
 #pragma unroll
     for (int q = 0; q < PRE; q++) {
       const int32_t c = cb + q * (TB / 64);
       d[q] = c < o1 ? a.chunk_ovf[c] : make_uint2(0u, CHUNK_EMPTY);
     }
-    chunk_group<V, X, K>(d, lane, lgT, a.sym != 0, a.ent_rc, ent_v, x, ys);
+    chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, a.ent_rc, ent_v, x, ys);
   }
   __syncthreads();
-  tile_final<V, X, K, EP>(a, t, xown, ys, s_red);
+  tile_final<V, X, K, EP, GEN>(a, t, xown, ys, s_red);
 }
 
 // One matrix: one workgroup per tile.  EP: with the solver epilogue (a
-// finished solver's done flag skips the whole launch).
-template <class V, class X, int K, bool EP>
+// finished solver's done flag skips the whole launch).  GEN: symmetric kind
+// and diagonal array.
+template <class V, class X, int K, bool EP, bool GEN>
 __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   __shared__ double s_red[TB / 64];
   extern __shared__ double ys[];
@@ -315,7 +318,7 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   if (EP && a.done && *a.done && !(a.active && *a.active)) return;
   const int32_t t = xcd_tile(blockIdx.x, a.ntiles);
   if (t >= a.ntiles) return;
-  tile_body<V, X, K, EP>(a, t, ys, s_red);
+  tile_body<V, X, K, EP, GEN>(a, t, ys, s_red);
 }
 
 // Many matrices in one launch: the (matrix, tile) items are split into 8
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
 // (workgroup j: items j, j + J, j + 2J, ...); the queues are ordered by cost,
 // so neighbouring items cost about the same and no counter is shared.
 // Items of a matrix whose solver has finished are skipped.
-template <class V, class X, int K, bool EP>
+template <class V, class X, int K, bool EP, bool GEN>
 __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restrict__ tasks,
                                                       const int2 *__restrict__ items,
                                                       const int32_t *__restrict__ qbeg) {
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restric
     const int2 w = items[it];
     const prod_task &a = tasks[w.x];
     if (EP && a.done && *a.done && !(a.active && *a.active)) continue;
-    tile_body<V, X, K, EP>(a, w.y, ys, s_red);
+    tile_body<V, X, K, EP, GEN>(a, w.y, ys, s_red);
     __syncthreads();  // ys and s_red are reused by the next item
   }
 }
@@ -349,7 +352,7 @@ static pars3_status raise_lds(F *kernel, size_t lds) {
   return PARS3_OK;
 }
 
-template <class V, class X, int K, bool EP>
+template <class V, class X, int K, bool EP, bool GEN>
 static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shift, const X *x, X *y, hipStream_t s,
                            const epilogue<X> &ep) {
   const layout &L = A->lay;
@@ -358,7 +361,7 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   const size_t lds = (size_t)L.T * KP<K> * sizeof(double);
   static bool raised = false;  // above the default dynamic LDS limit: ask for exactly what is needed
   if (!raised && lds + sizeof(double) * (TB / 64) > LDS_DEFAULT) {
-    P3_TRY(raise_lds(k_tile_product<V, X, K, EP>, (size_t)1024 * KP<K> * sizeof(double)));
+    P3_TRY(raise_lds(k_tile_product<V, X, K, EP, GEN>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
   prod_task a{};
@@ -389,7 +392,7 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   a.xs = ep.xs;
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
-  k_tile_product<V, X, K, EP><<<grid, TB, lds, s>>>(a);
+  k_tile_product<V, X, K, EP, GEN><<<grid, TB, lds, s>>>(a);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;
@@ -405,13 +408,23 @@ static pars3_status dispatch_k(pars3_matrix *A, const V *in_v, const V *ent_v, d
     // products with the solver epilogue are a kernel of their own
     ep = *(const epilogue<X> *)epv;
     if (k != 1) return fail(PARS3_EINVAL, "spmv: the solver epilogue takes one right-hand side");
-    return launch<V, X, 1, true>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    if (is_general(A)) return fail(PARS3_ESTATE, "spmv: the solver epilogue needs a skew matrix without diagonal");
+    return launch<V, X, 1, true, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+  }
+  if (is_general(A)) {
+    switch (k) {
+      case 1: return launch<V, X, 1, false, true>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+      case 2: return launch<V, X, 2, false, true>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+      case 4: return launch<V, X, 4, false, true>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+      case 8: return launch<V, X, 8, false, true>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+      default: return fail(PARS3_EINVAL, "spmv: k must be 1, 2, 4 or 8 (got %d)", k);
+    }
   }
   switch (k) {
-    case 1: return launch<V, X, 1, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
-    case 2: return launch<V, X, 2, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
-    case 4: return launch<V, X, 4, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
-    case 8: return launch<V, X, 8, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 1: return launch<V, X, 1, false, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 2: return launch<V, X, 2, false, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 4: return launch<V, X, 4, false, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
+    case 8: return launch<V, X, 8, false, false>(A, in_v, ent_v, (X)shift, xx, yy, s, ep);
     default: return fail(PARS3_EINVAL, "spmv: k must be 1, 2, 4 or 8 (got %d)", k);
   }
 }
@@ -532,41 +545,49 @@ pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, pr
   return PARS3_OK;
 }
 
-template <class V, class X, int K, bool EP>
+template <class V, class X, int K, bool EP, bool GEN>
 static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, const int32_t *qbeg, int32_t grid,
                                    int32_t maxT, hipStream_t s) {
   const size_t lds = (size_t)maxT * KP<K> * sizeof(double);
   static bool raised = false;
   if (!raised && lds + sizeof(double) * (TB / 64) + 64 > LDS_DEFAULT) {
-    P3_TRY(raise_lds(k_batch_product<V, X, K, EP>, (size_t)1024 * KP<K> * sizeof(double)));
+    P3_TRY(raise_lds(k_batch_product<V, X, K, EP, GEN>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
-  k_batch_product<V, X, K, EP><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
+  k_batch_product<V, X, K, EP, GEN><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
   P3_LAUNCHED();
   return PARS3_OK;
 }
 
-template <class V, class X>
-static pars3_status launch_batch_v(int k, bool ep, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
+template <class V, class X, bool GEN>
+static pars3_status launch_batch_g(int k, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
                                    int32_t grid, int32_t maxT, hipStream_t s) {
-  if (ep) {
-    if (k != 1) return fail(PARS3_EINVAL, "batch: the solver epilogue takes one right-hand side");
-    return launch_batch_k<V, X, 1, true>(tasks, items, qbeg, grid, maxT, s);
-  }
   switch (k) {
-    case 1: return launch_batch_k<V, X, 1, false>(tasks, items, qbeg, grid, maxT, s);
-    case 2: return launch_batch_k<V, X, 2, false>(tasks, items, qbeg, grid, maxT, s);
-    case 4: return launch_batch_k<V, X, 4, false>(tasks, items, qbeg, grid, maxT, s);
-    case 8: return launch_batch_k<V, X, 8, false>(tasks, items, qbeg, grid, maxT, s);
+    case 1: return launch_batch_k<V, X, 1, false, GEN>(tasks, items, qbeg, grid, maxT, s);
+    case 2: return launch_batch_k<V, X, 2, false, GEN>(tasks, items, qbeg, grid, maxT, s);
+    case 4: return launch_batch_k<V, X, 4, false, GEN>(tasks, items, qbeg, grid, maxT, s);
+    case 8: return launch_batch_k<V, X, 8, false, GEN>(tasks, items, qbeg, grid, maxT, s);
     default: return fail(PARS3_EINVAL, "batch: k must be 1, 2, 4 or 8 (got %d)", k);
   }
 }
 
-pars3_status launch_batch(int vkind, int k, bool ep, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
-                          int32_t grid, int32_t maxT, hipStream_t s) {
-  if (vkind == PARS3_F64) return launch_batch_v<double, double>(k, ep, tasks, items, qbeg, grid, maxT, s);
-  if (vkind == PARS3_F32) return launch_batch_v<float, float>(k, ep, tasks, items, qbeg, grid, maxT, s);
-  return launch_batch_v<uint16_t, float>(k, ep, tasks, items, qbeg, grid, maxT, s);
+template <class V, class X>
+static pars3_status launch_batch_v(int k, bool ep, bool gen, const prod_task *tasks, const int2 *items,
+                                   const int32_t *qbeg, int32_t grid, int32_t maxT, hipStream_t s) {
+  if (ep) {
+    if (k != 1) return fail(PARS3_EINVAL, "batch: the solver epilogue takes one right-hand side");
+    if (gen) return fail(PARS3_ESTATE, "batch: the solver epilogue needs skew matrices without diagonal");
+    return launch_batch_k<V, X, 1, true, false>(tasks, items, qbeg, grid, maxT, s);
+  }
+  if (gen) return launch_batch_g<V, X, true>(k, tasks, items, qbeg, grid, maxT, s);
+  return launch_batch_g<V, X, false>(k, tasks, items, qbeg, grid, maxT, s);
+}
+
+pars3_status launch_batch(int vkind, int k, bool ep, bool gen, const prod_task *tasks, const int2 *items,
+                          const int32_t *qbeg, int32_t grid, int32_t maxT, hipStream_t s) {
+  if (vkind == PARS3_F64) return launch_batch_v<double, double>(k, ep, gen, tasks, items, qbeg, grid, maxT, s);
+  if (vkind == PARS3_F32) return launch_batch_v<float, float>(k, ep, gen, tasks, items, qbeg, grid, maxT, s);
+  return launch_batch_v<uint16_t, float>(k, ep, gen, tasks, items, qbeg, grid, maxT, s);
 }
 
 }  // namespace p3

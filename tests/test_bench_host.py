@@ -17,8 +17,8 @@ def test_several_gpus_refused(capsys):
 
 
 def test_kernel_names():
-    assert bench.kernel_name("f64") == "p3::k_tile_product<double, double, 1, false>"
-    assert bench.kernel_name("bf16") == "p3::k_tile_product<unsigned short, float, 1, false>"
+    assert bench.kernel_name("f64") == "p3::k_tile_product<double, double, 1, false, false>"
+    assert bench.kernel_name("bf16") == "p3::k_tile_product<unsigned short, float, 1, false, false>"
 
 
 def test_algorithmic_bytes():
