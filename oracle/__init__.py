@@ -64,6 +64,7 @@ def _L():
             "or_bf16_to_f64": ([i64, _vp, _vp], None),
             "or_mrs": ([i32, _vp, _vp, _vp, d, _vp, _vp, d, i32, _vp, _vp], ctypes.c_int),
             "or_features": ([i32, _vp, _vp, _vp], ctypes.c_int),
+            "or_conflict_map": ([i32, _vp, _vp, _vp, i32, _vp, _vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -254,3 +255,25 @@ def bandwidth(L) -> int:
         return 0
     rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
     return int((rows - c).max())
+
+
+CONFLICT_FIELDS = ("first_row", "rows", "safe_inner", "safe_middle", "safe_outer", "conflict_inner",
+                   "conflict_middle", "conflict_outer", "reach", "partners", "halo")
+
+
+def conflict_map(L, part, nblocks: int, bounds=None) -> np.ndarray:
+    """Per-block conflict counts of a block-row distribution (Section 3,
+    Fig. 2): int64[nblocks, 11] with the columns of CONFLICT_FIELDS.  part:
+    the split class of every entry of L; bounds: nblocks + 1 row boundaries
+    or None (balanced)."""
+    n, rp, c, _ = _arrs(L)
+    pt = np.ascontiguousarray(part, np.int8)
+    b = None if bounds is None else np.ascontiguousarray(bounds, np.int64)
+    out = np.zeros((max(int(nblocks), 1), 11), np.int64)
+    r = _L().or_conflict_map(n, _p(rp), _p(c), _p(pt), int(nblocks), _p(b) if b is not None else None,
+                             out.ctypes.data)
+    if r == 1:
+        raise ValueError("bad block count or bounds")
+    if r != 0:
+        raise MemoryError("or_conflict_map")
+    return out[:nblocks]

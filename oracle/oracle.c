@@ -608,3 +608,75 @@ int or_features(int32_t n, const int32_t *rowptr, const int32_t *col, double *f)
   free(bw);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Conflict map of a block-row distribution (Section 3, Fig. 2).  Block p owns
+ * the rows [R_p, R_{p+1}) of the (reordered) matrix and the stored lower
+ * entries of those rows.  An entry (i, j) of block p is safe (R1) when its
+ * column j is also a row of block p: both of its products land in the block's
+ * own outputs.  It is conflicting (R2) when j < R_p: its transposed product
+ * writes y_j, which another block owns, and it reads x_j from there.  Block 0
+ * never has conflicting entries.
+ * bounds: nb + 1 nondecreasing row boundaries from 0 to n, or NULL for the
+ * balanced R_p = floor(p n / nb).  part: the split class of every entry
+ * (0 inner, 1 middle, 2 outer).  out: 11 values per block:
+ *   [0] R_p  [1] rows  [2..4] safe entries per part  [5..7] conflicting
+ *   entries per part  [8] reach = smallest column of a conflicting entry (R_p
+ *   when there is none)  [9] partners = distinct other blocks owning such a
+ *   column  [10] halo = distinct such columns (the x values the block reads
+ *   from others, and the partial sums it sends back).
+ * Returns 1 for nb < 1 or bad bounds, -1 when out of memory. */
+int or_conflict_map(int32_t n, const int32_t *rowptr, const int32_t *col, const int8_t *part, int32_t nb,
+                    const int64_t *bounds, int64_t *out) {
+  if (nb < 1) return 1;
+  int64_t *R = (int64_t *)malloc(((size_t)nb + 1) * sizeof(int64_t));
+  int32_t *owner = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  int32_t *seen_col = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  int32_t *seen_blk = (int32_t *)malloc((size_t)nb * sizeof(int32_t));
+  if (!R || !owner || !seen_col || !seen_blk) {
+    free(R); free(owner); free(seen_col); free(seen_blk);
+    return -1;
+  }
+  int bad = 0;
+  for (int32_t p = 0; p <= nb; p++) R[p] = bounds ? bounds[p] : ((int64_t)p * n) / nb;
+  if (R[0] != 0 || R[nb] != n) bad = 1;
+  for (int32_t p = 0; p < nb && !bad; p++)
+    if (R[p + 1] < R[p]) bad = 1;
+  if (bad) {
+    free(R); free(owner); free(seen_col); free(seen_blk);
+    return 1;
+  }
+  for (int32_t p = 0; p < nb; p++)
+    for (int64_t i = R[p]; i < R[p + 1]; i++) owner[i] = p;
+  for (int32_t i = 0; i < n; i++) seen_col[i] = -1;
+  for (int32_t p = 0; p < nb; p++) seen_blk[p] = -1;
+  for (int32_t p = 0; p < nb; p++) {
+    int64_t *o = out + (size_t)11 * p;
+    for (int k = 0; k < 11; k++) o[k] = 0;
+    o[0] = R[p];
+    o[1] = R[p + 1] - R[p];
+    o[8] = R[p];
+    for (int64_t i = R[p]; i < R[p + 1]; i++) {
+      for (int32_t e = rowptr[i]; e < rowptr[i + 1]; e++) {
+        int32_t j = col[e];
+        int k = part[e];
+        if (j >= R[p]) {
+          o[2 + k]++;
+          continue;
+        }
+        o[5 + k]++;
+        if (j < o[8]) o[8] = j;
+        if (seen_col[j] != p) {
+          seen_col[j] = p;
+          o[10]++;
+        }
+        if (seen_blk[owner[j]] != p) {
+          seen_blk[owner[j]] = p;
+          o[9]++;
+        }
+      }
+    }
+  }
+  free(R); free(owner); free(seen_col); free(seen_blk);
+  return 0;
+}
