@@ -159,6 +159,7 @@ def main(argv=None):
     ap.add_argument("--no-csr", action="store_true", help="skip the full-CSR comparison")
     ap.add_argument("--no-mrs", action="store_true", help="skip the MRS time-to-solution runs")
     ap.add_argument("--no-sym", action="store_true", help="skip the symmetric-with-diagonal product")
+    ap.add_argument("--no-conflicts", action="store_true", help="skip the conflict-map timing")
     ap.add_argument("--mrs-reps", type=int, default=3, help="timed solves per MRS precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix workload")
     ap.add_argument("--warm-cache", action="store_true",
@@ -331,6 +332,25 @@ def main(argv=None):
                                  "algorithmic_bytes": Bs, "time_vs_skew": round(sms / ms, 3)}
         del smats
         torch.cuda.synchronize()
+
+    # conflict map (Section 3, Fig. 2) of the reordered matrix for 8 equal row
+    # blocks (one per GPU of a node) and for the kernel's tiles: wall time of
+    # the synchronous call, share of conflicting entries, largest halo
+    if not args.no_conflicts:
+        T = info["tile_rows"]
+        nt = -(-n // T)
+        cm = {}
+        for cname, nb, bnd in (("blocks8", 8, None),
+                               ("tiles", nt, np.minimum(np.arange(nt + 1, dtype=np.int64) * T, n))):
+            p3.pars3_conflict_map(mats[0].h, nb, bnd)  # warm-up
+            t0 = time.perf_counter()
+            m = p3.pars3_conflict_map(mats[0].h, nb, bnd)
+            cms = (time.perf_counter() - t0) * 1e3
+            cm[cname] = {"blocks": nb, "ms": round(cms, 3),
+                         "conflicting_fraction": round(float(m[:, 5:8].sum()) / nnz, 5),
+                         "max_halo": int(m[:, 10].max()), "max_partners": int(m[:, 9].max()),
+                         "max_reach_rows": int((m[:, 0] - m[:, 8]).max())}
+        out["conflict_map"] = cm
 
     # MRS time to an FP64 relative residual of 1e-10 on (0.5 I + S) x = A 1:
     # FP64-only against mixed precision (FP32 or BF16 inner solves, FP64

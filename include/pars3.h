@@ -186,6 +186,33 @@ typedef struct {
 pars3_status pars3_set_profiling(pars3_matrix *A, int32_t enable);
 pars3_status pars3_get_profile(pars3_matrix *A, pars3_profile *out);
 
+/* Conflict map of a block-row distribution (Section 3, Fig. 2): block p owns
+ * rows [R_p, R_{p+1}) of the reordered matrix (after pars3_reorder; with
+ * permute = 0, of the given numbering) and the stored lower entries of those
+ * rows.  An entry (i, j) is safe (R1) when j >= R_p, conflicting (R2) when
+ * j < R_p: its transposed product lands in another block's output and it
+ * reads that block's x_j.  Block 0 never conflicts.  Per block (host output
+ * out[nblocks]):
+ *   first_row, rows     R_p and R_{p+1} - R_p
+ *   safe[3]             R1 entries of the inner, middle and outer parts
+ *   conflict[3]         R2 entries of the three parts
+ *   reach               smallest column of an R2 entry (R_p when none)
+ *   partners            distinct other blocks owning such columns
+ *   halo                distinct such columns: x values to receive and
+ *                       partial sums to send back for one product
+ * bounds: host array of nblocks + 1 nondecreasing row boundaries from 0 to n
+ * (empty blocks allowed), or NULL for R_p = floor(p n / nblocks).  Integer
+ * work on the GPU; synchronous.  Errors: ESTATE before pars3_reorder; EINVAL
+ * for nblocks < 1, bad bounds or a NULL output. */
+typedef struct {
+  int64_t first_row, rows;
+  int64_t safe[3];
+  int64_t conflict[3];
+  int64_t reach, partners, halo;
+} pars3_block_conflicts;
+pars3_status pars3_conflict_map(const pars3_matrix *A, int32_t nblocks, const int64_t *bounds,
+                                pars3_block_conflicts *out, void *stream);
+
 /* Full-CSR comparison path (the storage that keeps every nonzero, Section 1).
  * pars3_csr_create builds, on the GPU, the full CSR of S (both triangles,
  * 2*nnz entries, columns ascending in every row; with a diagonal array, D + S

@@ -63,6 +63,12 @@ class Profile(ctypes.Structure):
                 ("ms_other", ctypes.c_double)]
 
 
+class BlockConflicts(ctypes.Structure):
+    _fields_ = [("first_row", ctypes.c_int64), ("rows", ctypes.c_int64), ("safe", ctypes.c_int64 * 3),
+                ("conflict", ctypes.c_int64 * 3), ("reach", ctypes.c_int64), ("partners", ctypes.c_int64),
+                ("halo", ctypes.c_int64)]
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("params", SplitParams), ("us", ctypes.c_double)]
 
@@ -106,6 +112,7 @@ SIGNATURES = {
     "pars3_csr_spmv": ([_vp, _d, _vp, _vp, _i32, _vp], _st),
     "pars3_csr_get": ([_vp, _vp, _vp, _vp], _st),
     "pars3_csr_size": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _st),
+    "pars3_conflict_map": ([_vp, _i32, _vp, ctypes.POINTER(BlockConflicts), _vp], _st),
     "pars3_csr_destroy": ([_vp], None),
     "pars3_features": ([_vp, _vp], _st),
     "pars3_tune_grid_default": ([_i32, _vp, _i32, ctypes.POINTER(_i32)], _st),
@@ -303,6 +310,20 @@ def pars3_csr_create(h, order=ORDER_RCM, value_dtype=F64):
 
 def pars3_csr_spmv(c, shift, x, y, engine=0, stream=None):
     _check(lib().pars3_csr_spmv(c, float(shift), _ptr(x), _ptr(y), int(engine), _stream(stream)), "pars3_csr_spmv")
+
+
+CONFLICT_FIELDS = ("first_row", "rows", "safe_inner", "safe_middle", "safe_outer", "conflict_inner",
+                   "conflict_middle", "conflict_outer", "reach", "partners", "halo")
+
+
+def pars3_conflict_map(h, nblocks, bounds=None, stream=None) -> np.ndarray:
+    """Per-block conflict counts, int64[nblocks, 11] with the columns of
+    CONFLICT_FIELDS."""
+    nb = int(nblocks)
+    out = (BlockConflicts * max(nb, 1))()
+    b = None if bounds is None else np.ascontiguousarray(bounds, np.int64)
+    _check(lib().pars3_conflict_map(h, nb, _ptr(b), out, _stream(stream)), "pars3_conflict_map")
+    return np.frombuffer(out, np.int64).reshape(-1, 11)[:nb].copy()  # 11 packed int64 per block
 
 
 def pars3_csr_size(c):
@@ -585,6 +606,9 @@ class Matrix:
 
     def features(self):
         return pars3_features(self.h)
+
+    def conflict_map(self, nblocks, bounds=None):
+        return pars3_conflict_map(self.h, nblocks, bounds)
 
     def diagonal(self):
         """The diagonal array in the reordered numbering."""
