@@ -240,6 +240,44 @@ def residual(L, alpha: float, b, x) -> float:
     return float(np.linalg.norm(r)) / (nb if nb > 0 else 1.0)
 
 
+def skew_form(L, alpha: float, diag):
+    """Shifted skew-symmetric form of A = J + S, J = alpha*I + D positive
+    definite and diagonal (Section 1 names A = J - S with J symmetric positive
+    semi-definite as reducible to the alpha*I + S form).  With J = diag(j_i)
+    the two-sided scaling J^(-1/2) A J^(-1/2) = I + S~ is exact, S~_ik =
+    s_ik / sqrt(j_i j_k) still skew.  Returns (L~, ds) with ds_i =
+    1 / sqrt(j_i); the solution of A x = b is x = ds * x~ where
+    (I + S~) x~ = ds * b."""
+    n, rp, c, v = _arrs(L)
+    j = float(alpha) + np.asarray(diag, np.float64)
+    if j.shape != (n,):
+        raise ValueError("diag must hold n values")
+    if n and not np.all(j > 0):
+        raise ValueError("alpha*I + D is not positive definite")
+    ds = 1.0 / np.sqrt(j)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    return SimpleNamespace(n=n, rowptr=rp, col=c, val=v * ds[rows] * ds[c], nnz=int(c.shape[0])), ds
+
+
+def mrs_shifted(L, alpha: float, diag, b, x0=None, tol: float = 1e-10, maxit: int = 1000):
+    """MRS for (alpha*I + D + S) x = b through the shifted skew-symmetric
+    form: MRS on (I + S~) x~ = ds * b from x~0 = x0 / ds, to the tolerance
+    tol / sqrt(max j / min j), which bounds the relative residual of the
+    returned x = ds * x~ in the original system by tol.  Returns (x, info,
+    hist); info["relres"] is that original-system residual."""
+    Lt, ds = skew_form(L, alpha, diag)
+    j = float(alpha) + np.asarray(diag, np.float64)
+    cond = float(j.max() / j.min()) if len(j) else 1.0
+    b = np.asarray(b, np.float64)
+    xt0 = None if x0 is None else np.asarray(x0, np.float64) / ds
+    xt, info, hist = mrs(Lt, 1.0, ds * b, xt0, tol / np.sqrt(cond), maxit)
+    x = ds * xt
+    r = b - spmv(L, alpha, x, diag=diag)
+    nb = float(np.linalg.norm(b))
+    info = dict(info, relres=float(np.linalg.norm(r)) / (nb if nb > 0 else 1.0), inner_tol=tol / np.sqrt(cond))
+    return x, info, hist
+
+
 def features(L) -> np.ndarray:
     n, rp, c, _ = _arrs(L)
     f = np.zeros(32, np.float64)
