@@ -133,6 +133,19 @@ pars3_status pars3_get_kind(const pars3_matrix *A, int32_t *kind, int32_t *has_d
  * diagonal.  Synchronous. */
 pars3_status pars3_get_diagonal(const pars3_matrix *A, double *out);
 
+/* Shifted skew-symmetric form (Section 1: a system A = J - S with J symmetric
+ * positive semi-definite is brought to the alpha*I + S form).  For a skew
+ * handle with J = alpha*I + D diagonal and positive definite (D = 0 when the
+ * handle has no diagonal array, then alpha > 0), the two-sided scaling
+ *   J^(-1/2) (alpha*I + D + S) J^(-1/2) = I + S~,  S~ = J^(-1/2) S J^(-1/2)
+ * is exact and S~ is skew.  *out receives a new handle holding S~ (caller
+ * owns it; pars3_destroy), with A's structure, permutation and split
+ * parameters, already reordered; solve (I + S~) x~ = b~ with b~_i =
+ * b_i / sqrt(alpha + d_i) and take x_i = x~_i / sqrt(alpha + d_i).
+ * Synchronous.  Errors: ESTATE before pars3_reorder or for a symmetric
+ * handle; EINVAL when some alpha + d_i <= 0. */
+pars3_status pars3_skew_form(const pars3_matrix *A, double alpha, pars3_matrix **out, void *stream);
+
 /* Frees every device and host resource of the handle.  NULL is allowed. */
 void pars3_destroy(pars3_matrix *A);
 
@@ -327,9 +340,13 @@ typedef struct {
   double time_ms;      /* wall time of the call */
 } pars3_mrs_info;
 
-/* The solver needs A = alpha*I + S with S skew-symmetric: a handle made by
- * pars3_create_sss with PARS3_SYMMETRIC or with a diagonal array gives
- * ESTATE. */
+/* The solver needs S skew-symmetric: a handle made by pars3_create_sss with
+ * PARS3_SYMMETRIC gives ESTATE.  A skew handle with a diagonal array D is
+ * solved for (alpha*I + D + S) x = b through its shifted skew-symmetric form
+ * (see pars3_skew_form): MRS on (I + S~) x~ = J^(-1/2) b to the tolerance
+ * tol / sqrt(max j / min j), x = J^(-1/2) x~; info->relres is then the
+ * original system's residual and hist the scaled system's.  EINVAL when
+ * J = alpha*I + D is not positive definite. */
 void pars3_mrs_opts_default(pars3_mrs_opts *o);
 pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, double *x, const pars3_mrs_opts *opts,
                              pars3_mrs_info *info, void *stream);

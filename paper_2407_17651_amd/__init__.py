@@ -99,6 +99,7 @@ SIGNATURES = {
     "pars3_create_sss": ([_i64, _i64, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_vp)], _st),
     "pars3_get_kind": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)], _st),
     "pars3_get_diagonal": ([_vp, _vp], _st),
+    "pars3_skew_form": ([_vp, _d, ctypes.POINTER(_vp), _vp], _st),
     "pars3_destroy": ([_vp], None),
     "pars3_reorder": ([_vp, ctypes.POINTER(SplitParams), _vp], _st),
     "pars3_spmv": ([_vp, _d, _vp, _vp, _i32, _i32, _i32, _vp], _st),
@@ -235,6 +236,12 @@ def pars3_create_sss(n, nnz, rowptr, col, val, diag=None, kind=SKEW):
     _check(lib().pars3_create_sss(n, nnz, _ptr(rp), _ptr(c), _ptr(v), dp, int(kind), ctypes.byref(h)),
            "pars3_create_sss")
     return h
+
+
+def pars3_skew_form(h, alpha, stream=None):
+    out = _vp()
+    _check(lib().pars3_skew_form(h, float(alpha), ctypes.byref(out), _stream(stream)), "pars3_skew_form")
+    return out
 
 
 def pars3_get_kind(h):
@@ -566,6 +573,18 @@ class Matrix:
             self.h = pars3_create(self.n, self.nnz, L.rowptr, L.col, L.val)
         else:
             self.h = pars3_create_sss(self.n, self.nnz, L.rowptr, L.col, L.val, diag, self.kind)
+
+    @classmethod
+    def _adopt(cls, h, n, nnz, kind=SKEW):
+        """Wraps a handle the library created (the wrapper owns it)."""
+        m = cls.__new__(cls)
+        m.n, m.nnz, m.kind, m.h = int(n), int(nnz), kind, h
+        return m
+
+    def skew_form(self, alpha):
+        """The shifted skew-symmetric form I + S~ of alpha*I + D + S (a new
+        reordered handle holding S~)."""
+        return Matrix._adopt(pars3_skew_form(self.h, alpha), self.n, self.nnz)
 
     def close(self):
         if self.h:

@@ -74,6 +74,13 @@ extern "C" pars3_status pars3_create_sss(int64_t n, int64_t nnz, const int32_t *
       return bail(fail(PARS3_ENOMEM, "create: device allocation failed: %s", hipGetErrorString(e)));
     if (n > 0 && (e = hipMemcpy(A->diag.p, diag, n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
       return bail(fail(PARS3_EHIP, "create: copy to device failed: %s", hipGetErrorString(e)));
+    if (n > 0) {
+      A->dmin = A->dmax = diag[0];
+      for (int64_t i = 1; i < n; i++) {
+        A->dmin = std::min(A->dmin, diag[i]);
+        A->dmax = std::max(A->dmax, diag[i]);
+      }
+    }
   }
   *out = A;
   return PARS3_OK;
@@ -95,6 +102,7 @@ extern "C" pars3_status pars3_get_diagonal(const pars3_matrix *A, double *out) {
 }
 
 pars3_matrix::~pars3_matrix() {
+  p3::skew_shadow_free(shadow);
   p3::mrs_ws_free(mrs);
   if (solver_stream) (void)hipStreamDestroy(solver_stream);
   for (auto &v : prof.ev)
@@ -159,6 +167,8 @@ extern "C" pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params 
     A->perm_kind = p.permute;
   }
   A->split_done = false;
+  p3::skew_shadow_free(A->shadow);  // built for the previous split
+  A->shadow = nullptr;
   P3_TRY(p3::split_and_layout(A, p, s));
   P3_HIP(hipStreamSynchronize(s));
   A->split_done = true;

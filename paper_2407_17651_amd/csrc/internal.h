@@ -184,6 +184,11 @@ void mrs_ws_free(mrs_ws *w);
 
 }  // namespace p3
 
+namespace p3 {
+struct skew_shadow;  // skewform.hip
+void skew_shadow_free(skew_shadow *sh);
+}  // namespace p3
+
 struct pars3_matrix {
   int64_t n = 0, nnz = 0;
   int device = 0;
@@ -192,9 +197,13 @@ struct pars3_matrix {
   // input, original numbering; diag: the SSS diagonal array (empty: D = 0)
   p3::dbuf<int32_t> rowptr, col;
   p3::dbuf<double> val, diag;
-  // the diagonal in the reordered numbering, FP64 and rounded to FP32
+  // the diagonal in the reordered numbering, FP64 and rounded to FP32, and
+  // its smallest and largest entry (host, from the caller's array)
   p3::dbuf<double> pdiag;
   p3::dbuf<float> pdiag32;
+  double dmin = 0.0, dmax = 0.0;
+  // scaled skew form for the MRS solver (skewform.hip), created on first use
+  p3::skew_shadow *shadow = nullptr;
   // reordering
   bool perm_done = false;
   int32_t perm_kind = -1;  // 1 RCM, 0 identity
@@ -360,6 +369,9 @@ pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, pr
 // gen: some task is symmetric or has a diagonal array.
 pars3_status launch_batch(int vkind, int k, bool ep, bool gen, const prod_task *tasks, const int2 *items,
                           const int32_t *qbeg, int32_t grid, int32_t maxT, hipStream_t s);
+// skewform.hip: MRS for alpha*I + D + S through its shifted skew form
+pars3_status mrs_shifted(pars3_matrix *A, double alpha, const double *b, double *x, const pars3_mrs_opts &o,
+                         pars3_mrs_info *info, hipStream_t s);
 // A symmetric matrix or one with a diagonal array (the general kernels).
 inline bool is_general(const pars3_matrix *A) { return A->kind != PARS3_SKEW || A->diag.p != nullptr; }
 // Product with an optional epilogue; value_dtype selects FP32 or BF16 values

@@ -307,8 +307,7 @@ extern "C" pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const dou
   using namespace p3;
   if (!A) return fail(PARS3_EINVAL, "mrs: NULL handle");
   if (!A->split_done) return fail(PARS3_ESTATE, "mrs: call pars3_reorder first");
-  if (A->kind != PARS3_SKEW || A->diag.p)
-    return fail(PARS3_ESTATE, "mrs: the solver needs alpha*I + S with S skew-symmetric and no diagonal array");
+  if (A->kind != PARS3_SKEW) return fail(PARS3_ESTATE, "mrs: the solver needs S skew-symmetric");
   pars3_mrs_opts o;
   if (opts) o = *opts;
   else pars3_mrs_opts_default(&o);
@@ -325,6 +324,8 @@ extern "C" pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const dou
     return fail(PARS3_ESTATE, "mrs: BF16 inner solves need value_dtype = PARS3_BF16 with keep_fp64");
   const int64_t n = A->n;
   if (n > 0 && (!b || !x)) return fail(PARS3_EINVAL, "mrs: NULL vector");
+  // alpha*I + D + S: through its shifted skew form I + S~
+  if (A->diag.p) return mrs_shifted(A, alpha, b, x, o, info, (hipStream_t)stream);
   pars3_mrs_info inf{};
   if (n == 0) {
     if (info) *info = inf;
