@@ -37,24 +37,19 @@ static constexpr int PRE = CHUNKS_FIXED / (TB / 64);  // chunks per wavefront wh
 template <int K>
 constexpr int KP = K == 1 ? 1 : K + 1;
 
+// Raw loads of stored values (normal, and nontemporal for a last use) and
+// their conversion to the vector type; a BF16 value is the high half of an
+// FP32 one.  The conversion is kept apart from the load so that a group of
+// loads can all be issued before the first result is used.
 template <class V>
-struct vload;
-template <>
-struct vload<double> {
-  static __device__ __forceinline__ double nt(const double *p, int64_t i) { return __builtin_nontemporal_load(p + i); }
-  static __device__ __forceinline__ double ld(const double *p, int64_t i) { return p[i]; }
-};
-template <>
-struct vload<float> {
-  static __device__ __forceinline__ float nt(const float *p, int64_t i) { return __builtin_nontemporal_load(p + i); }
-  static __device__ __forceinline__ float ld(const float *p, int64_t i) { return p[i]; }
-};
-template <>
-struct vload<uint16_t> {
-  static __device__ __forceinline__ float nt(const uint16_t *p, int64_t i) {
-    return __uint_as_float((uint32_t)__builtin_nontemporal_load(p + i) << 16);
+struct vload {
+  static __device__ __forceinline__ V nt(const V *p, int64_t i) { return __builtin_nontemporal_load(p + i); }
+  static __device__ __forceinline__ V ld(const V *p, int64_t i) { return p[i]; }
+  template <class X>
+  static __device__ __forceinline__ X cvt(V v) {
+    if constexpr (std::is_same<V, uint16_t>::value) return (X)__uint_as_float((uint32_t)v << 16);
+    else return (X)v;
   }
-  static __device__ __forceinline__ float ld(const uint16_t *p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
 };
 
 // The k values of one row of x (or y) as 16-byte vector accesses where the
@@ -109,10 +104,36 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
 // Loads of one group of chunks (one per q) and their products added into
 // the LDS row sums; a descriptor with .y == CHUNK_EMPTY is skipped.
 // sym: the column side adds l_ij x_i (symmetric S) instead of subtracting it.
+// Every load of the group is issued before any result is used.  Lanes past a
+// chunk's end re-read its last entry (in bounds, the same cache line) and are
+// masked only when their product is added; the only branches around loads
+// test the wave-uniform descriptors.  (A lane-divergent branch around a load
+// whose result is used inside it makes the compiler wait for that load before
+// the next one is issued.)
 template <class V, class X, int K>
 __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
                                             const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
                                             const X *__restrict__ x, double *ys) {
+  uint32_t rc[PRE];
+  V vv[PRE];
+#pragma unroll
+  for (int q = 0; q < PRE; q++) {
+    rc[q] = 0u;
+    vv[q] = (V)0;
+    if (d[q].y != CHUNK_EMPTY) {
+      const int32_t len = (int32_t)(d[q].y & 127u) + 1;
+      const int64_t e = (int64_t)d[q].x + min(lane, len - 1);
+      // the column side reads a block first and leaves it in L2; the row
+      // side is its last use (nontemporal)
+      if ((d[q].y >> 7) & 1u) {
+        rc[q] = ent_rc[e];
+        vv[q] = vload<V>::ld(ent_v, e);
+      } else {
+        rc[q] = __builtin_nontemporal_load(ent_rc + e);
+        vv[q] = vload<V>::nt(ent_v, e);
+      }
+    }
+  }
   int32_t slot[PRE], xrow[PRE];
   X coef[PRE], xv[PRE][K];
 #pragma unroll
@@ -124,29 +145,16 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
       const int32_t len = (int32_t)(d[q].y & 127u) + 1;
       const bool col_side = (d[q].y >> 7) & 1u;
       const int32_t other = (int32_t)(d[q].y >> 8);
-      if (lane < len) {
-        const int64_t e = (int64_t)d[q].x + lane;
-        // the column side reads a block first and leaves it in L2; the row
-        // side is its last use (nontemporal)
-        uint32_t rc;
-        X val;
-        if (col_side) {
-          rc = ent_rc[e];
-          val = (X)vload<V>::ld(ent_v, e);
-        } else {
-          rc = __builtin_nontemporal_load(ent_rc + e);
-          val = (X)vload<V>::nt(ent_v, e);
-        }
-        const int32_t ri = (int32_t)(rc >> 16), cj = (int32_t)(rc & 0xffffu);
-        slot[q] = col_side ? cj : ri;
-        xrow[q] = (other << lgT) + (col_side ? ri : cj);
-        coef[q] = col_side && !sym ? -val : val;
-      }
+      const int32_t ri = (int32_t)(rc[q] >> 16), cj = (int32_t)(rc[q] & 0xffffu);
+      const X val = vload<V>::template cvt<X>(vv[q]);
+      slot[q] = lane < len ? (col_side ? cj : ri) : -1;
+      xrow[q] = (other << lgT) + (col_side ? ri : cj);
+      coef[q] = col_side && !sym ? -val : val;
     }
   }
 #pragma unroll
   for (int q = 0; q < PRE; q++) {
-    if (slot[q] >= 0) {
+    if (d[q].y != CHUNK_EMPTY) {
       rowvec<X, K>::load(x, xrow[q], xv[q]);
     } else {
 #pragma unroll
@@ -197,21 +205,36 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
     X acc[K];
 #pragma unroll
     for (int c = 0; c < K; c++) acc[c] = (X)ys[r * KP<K> + c];
-    for (int32_t k = 1; k <= w_in; k++) {
-      const int64_t bse = (int64_t)(k - 1) * n;
-      if (i - k >= 0) {
-        const X l = (X)vload<V>::nt(dia, bse + i);
-        if (l != (X)0) {
+    // inner band in both directions, KB diagonals at a time: their loads are
+    // all issued before the first is used (indices clamped into range; terms
+    // outside the matrix, past w_in or on structural zeros are masked after)
+    constexpr int KB = K <= 2 ? 4 : (K == 4 ? 2 : 1);
+    for (int32_t k0 = 1; k0 <= w_in; k0 += KB) {
+      V lv[KB], uv[KB];
+      X xl[KB][K], xu[KB][K];
 #pragma unroll
-          for (int c = 0; c < K; c++) acc[c] += l * x[(i - k) * K + c];
-        }
+      for (int u = 0; u < KB; u++) {
+        const int32_t k = min(k0 + u, w_in);
+        const int64_t bse = (int64_t)(k - 1) * n;
+        const int64_t il = i - k >= 0 ? i - k : 0, iu = i + k < n ? i + k : (int64_t)n - 1;
+        lv[u] = vload<V>::nt(dia, bse + i);
+        uv[u] = vload<V>::nt(dia, bse + iu);
+        rowvec<X, K>::load(x, il, xl[u]);
+        rowvec<X, K>::load(x, iu, xu[u]);
       }
-      if (i + k < n) {
-        const X l = (X)vload<V>::nt(dia, bse + i + k);
-        if (l != (X)0) {
-          const X lu = sym ? l : -l;  // S_i,i+k
 #pragma unroll
-          for (int c = 0; c < K; c++) acc[c] += lu * x[(i + k) * K + c];
+      for (int u = 0; u < KB; u++) {
+        const int32_t k = k0 + u;
+        const X l = k <= w_in && i - k >= 0 ? vload<V>::template cvt<X>(lv[u]) : (X)0;  // S_i,i-k
+        const X m = k <= w_in && i + k < n ? vload<V>::template cvt<X>(uv[u]) : (X)0;
+        const X lu = sym ? m : -m;  // S_i,i+k
+        if (l != (X)0) {
+#pragma unroll
+          for (int c = 0; c < K; c++) acc[c] += l * xl[u][c];
+        }
+        if (m != (X)0) {
+#pragma unroll
+          for (int c = 0; c < K; c++) acc[c] += lu * xu[u][c];
         }
       }
     }
