@@ -37,18 +37,53 @@ static constexpr int PRE = CHUNKS_FIXED / (TB / 64);  // chunks per wavefront wh
 template <int K>
 constexpr int KP = K == 1 ? 1 : K + 1;
 
+// Device arrays seen as global-address-space pointers.  Loads through them
+// are global loads (scalar loads where the address is wave-uniform) also when
+// the pointer itself was read from memory, as in the batched tasks; through a
+// generic pointer they would be flat loads, which the compiler waits for
+// together with the LDS operations.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <class T>
+using gmut = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> glb(const T *p) {
+  return (gptr<T>)p;
+}
+template <class T>
+__device__ __forceinline__ gmut<T> glbw(T *p) {
+  return (gmut<T>)p;
+}
+// A chunk descriptor read as one 64-bit word (.x in the low half).
+__device__ __forceinline__ uint2 load_desc(const uint2 *p, int64_t i) {
+  const uint64_t v = glb((const uint64_t *)p)[i];
+  return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
 // Raw loads of stored values (normal, and nontemporal for a last use) and
 // their conversion to the vector type; a BF16 value is the high half of an
 // FP32 one.  The conversion is kept apart from the load so that a group of
 // loads can all be issued before the first result is used.
 template <class V>
 struct vload {
-  static __device__ __forceinline__ V nt(const V *p, int64_t i) { return __builtin_nontemporal_load(p + i); }
-  static __device__ __forceinline__ V ld(const V *p, int64_t i) { return p[i]; }
+  // register type of a raw value: BF16 bits are held zero-extended in a full
+  // 32-bit register (two of them packed in one register would make the
+  // compiler wait for the first load before packing)
+  using R = typename std::conditional<sizeof(V) == 2, uint32_t, V>::type;
+  static __device__ __forceinline__ R nt(gptr<V> p, int64_t i) { return (R)__builtin_nontemporal_load(p + i); }
+  static __device__ __forceinline__ R ld(gptr<V> p, int64_t i) { return (R)p[i]; }
   template <class X>
-  static __device__ __forceinline__ X cvt(V v) {
-    if constexpr (std::is_same<V, uint16_t>::value) return (X)__uint_as_float((uint32_t)v << 16);
-    else return (X)v;
+  static __device__ __forceinline__ X cvt(R v) {
+    if constexpr (sizeof(V) == 2) {
+      // the empty statement keeps the shift here: without it the compiler
+      // moves the shift up into the branch of the load, right after it, and
+      // has to wait for that load there
+      uint32_t u = v;
+      asm volatile("" : "+v"(u));
+      return (X)__uint_as_float(u << 16);
+    } else {
+      return (X)v;
+    }
   }
 };
 
@@ -59,32 +94,29 @@ template <class X, int K>
 struct rowvec {
   static constexpr int W = 16 / sizeof(X);  // values per 16 bytes
   static constexpr bool VEC = K >= W && K % W == 0;
-  static __device__ __forceinline__ void load(const X *__restrict__ p, int64_t row, X (&v)[K]) {
+  typedef X V4 __attribute__((ext_vector_type(W)));
+  static __device__ __forceinline__ void load(gptr<X> p, int64_t row, X (&v)[K]) {
     if constexpr (VEC) {
-      using V4 = typename std::conditional<sizeof(X) == 8, double2, float4>::type;
-      const V4 *q = reinterpret_cast<const V4 *>(p + row * K);
+      gptr<V4> q = (gptr<V4>)(p + row * K);
 #pragma unroll
       for (int u = 0; u < K / W; u++) {
         const V4 t = q[u];
-        const X *tt = reinterpret_cast<const X *>(&t);
 #pragma unroll
-        for (int w = 0; w < W; w++) v[u * W + w] = tt[w];
+        for (int w = 0; w < W; w++) v[u * W + w] = t[w];
       }
     } else {
 #pragma unroll
       for (int c = 0; c < K; c++) v[c] = p[row * K + c];
     }
   }
-  static __device__ __forceinline__ void store(X *__restrict__ p, int64_t row, const X (&v)[K]) {
+  static __device__ __forceinline__ void store(gmut<X> p, int64_t row, const X (&v)[K]) {
     if constexpr (VEC) {
-      using V4 = typename std::conditional<sizeof(X) == 8, double2, float4>::type;
-      V4 *q = reinterpret_cast<V4 *>(p + row * K);
+      gmut<V4> q = (gmut<V4>)(p + row * K);
 #pragma unroll
       for (int u = 0; u < K / W; u++) {
         V4 t;
-        X *tt = reinterpret_cast<X *>(&t);
 #pragma unroll
-        for (int w = 0; w < W; w++) tt[w] = v[u * W + w];
+        for (int w = 0; w < W; w++) t[w] = v[u * W + w];
         q[u] = t;
       }
     } else {
@@ -112,14 +144,13 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
 // the next one is issued.)
 template <class V, class X, int K>
 __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
-                                            const uint32_t *__restrict__ ent_rc, const V *__restrict__ ent_v,
-                                            const X *__restrict__ x, double *ys) {
+                                            gptr<uint32_t> ent_rc, gptr<V> ent_v, gptr<X> x, double *ys) {
   uint32_t rc[PRE];
-  V vv[PRE];
+  typename vload<V>::R vv[PRE];
 #pragma unroll
   for (int q = 0; q < PRE; q++) {
     rc[q] = 0u;
-    vv[q] = (V)0;
+    vv[q] = 0;
     if (d[q].y != CHUNK_EMPTY) {
       const int32_t len = (int32_t)(d[q].y & 127u) + 1;
       const int64_t e = (int64_t)d[q].x + min(lane, len - 1);
@@ -174,11 +205,11 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
 template <class V, class X, int K, bool EP, bool GEN>
 __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const X (&xown)[K], const double *ys,
                                            double *s_red) {
-  const V *__restrict__ dia = (const V *)a.dia;
-  const X *__restrict__ x = (const X *)a.x;
-  X *__restrict__ y = (X *)a.y;
-  const X *__restrict__ z = (const X *)a.z;
-  const X *__restrict__ dg = GEN ? (const X *)a.dg : nullptr;
+  gptr<V> dia = glb((const V *)a.dia);
+  gptr<X> x = glb((const X *)a.x);
+  gmut<X> y = glbw((X *)a.y);
+  gptr<X> z = glb((const X *)a.z);
+  gptr<X> dg = GEN ? glb((const X *)a.dg) : nullptr;
   const int32_t n = a.n, w_in = a.w_in;
   const X shift = (X)a.shift;
   const bool sym = GEN && a.sym != 0;
@@ -189,14 +220,15 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
   bool upd = false;
   double vd = 0.0, ve = 0.0, vg = 1.0, vc = 0.0, vn = 0.0;
   if constexpr (EP) {
-    if (a.scale) sc = (X)*a.scale;
-    if (K == 1 && a.vec && *a.active) {
+    if (a.scale) sc = (X)glb(a.scale)[0];
+    if (K == 1 && a.vec && glb(a.active)[0]) {
+      gptr<double> vec = glb(a.vec);
       upd = true;
-      vd = a.vec[0];
-      ve = a.vec[1];
-      vg = a.vec[2];
-      vc = a.vec[3];
-      vn = a.vec[4];
+      vd = vec[0];
+      ve = vec[1];
+      vg = vec[2];
+      vc = vec[3];
+      vn = vec[4];
     }
   }
   double sq = 0.0;
@@ -210,7 +242,7 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
     // outside the matrix, past w_in or on structural zeros are masked after)
     constexpr int KB = K <= 2 ? 4 : (K == 4 ? 2 : 1);
     for (int32_t k0 = 1; k0 <= w_in; k0 += KB) {
-      V lv[KB], uv[KB];
+      typename vload<V>::R lv[KB], uv[KB];
       X xl[KB][K], xu[KB][K];
 #pragma unroll
       for (int u = 0; u < KB; u++) {
@@ -245,13 +277,13 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
       acc[c] = EP ? sh * xi + sc * acc[c] : sh * xi + acc[c];
     }
     if (EP && z) {
-      const X zb = (X)*a.beta;
+      const X zb = (X)glb(a.beta)[0];
 #pragma unroll
       for (int c = 0; c < K; c++) acc[c] += zb * z[i * K + c];
       if (upd) {
-        X *__restrict__ p2 = (X *)a.p2;
-        X *__restrict__ xs = (X *)a.xs;
-        const X *__restrict__ p1 = (const X *)a.p1;
+        gmut<X> p2 = glbw((X *)a.p2);
+        gmut<X> xs = glbw((X *)a.xs);
+        gptr<X> p1 = glb((const X *)a.p1);
         const double pn = ((double)z[i] * vn - vd * (double)p1[i] - ve * (double)p2[i]) / vg;
         p2[i] = (X)pn;
         xs[i] = (X)((double)xs[i] + vc * pn);
@@ -289,13 +321,10 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
 // without it the product is the skew one with the scalar shift only.
 template <class V, class X, int K, bool EP, bool GEN>
 __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double *ys, double *s_red) {
-  const V *__restrict__ ent_v = (const V *)a.ent_v;
-  const V *__restrict__ dia = (const V *)a.dia;
-  const X *__restrict__ x = (const X *)a.x;
-  X *__restrict__ y = (X *)a.y;
-  const X *__restrict__ z = (const X *)a.z;
-  const int32_t n = a.n, lgT = a.lgT, w_in = a.w_in;
-  const X shift = (X)a.shift;
+  gptr<V> ent_v = glb((const V *)a.ent_v);
+  gptr<uint32_t> ent_rc = glb(a.ent_rc);
+  gptr<X> x = glb((const X *)a.x);
+  const int32_t n = a.n, lgT = a.lgT;
   const int32_t T = 1 << lgT;
   const int32_t r0 = t << lgT;
   const int32_t rows = min(T, n - r0);
@@ -305,8 +334,8 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   // thread's first own row are requested before anything else
   uint2 d[PRE];
 #pragma unroll
-  for (int q = 0; q < PRE; q++) d[q] = a.chunk_fix[(int64_t)t * CHUNKS_FIXED + wave + q * (TB / 64)];
-  const int32_t o0 = a.ovf_ptr[t], o1 = a.ovf_ptr[t + 1];
+  for (int q = 0; q < PRE; q++) d[q] = load_desc(a.chunk_fix, (int64_t)t * CHUNKS_FIXED + wave + q * (TB / 64));
+  const int32_t o0 = glb(a.ovf_ptr)[t], o1 = glb(a.ovf_ptr)[t + 1];
   X xown[K];
   if ((int32_t)threadIdx.x < rows) {
     rowvec<X, K>::load(x, (int64_t)r0 + threadIdx.x, xown);
@@ -316,14 +345,14 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   }
   for (int32_t s = threadIdx.x; s < rows * KP<K>; s += TB) ys[s] = 0.0;
   __syncthreads();
-  chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, a.ent_rc, ent_v, x, ys);
+  chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
   for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
 #pragma unroll
     for (int q = 0; q < PRE; q++) {
       const int32_t c = cb + q * (TB / 64);
-      d[q] = c < o1 ? a.chunk_ovf[c] : make_uint2(0u, CHUNK_EMPTY);
+      d[q] = c < o1 ? load_desc(a.chunk_ovf, c) : make_uint2(0u, CHUNK_EMPTY);
     }
-    chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, a.ent_rc, ent_v, x, ys);
+    chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
   }
   __syncthreads();
   tile_final<V, X, K, EP, GEN>(a, t, xown, ys, s_red);
@@ -338,7 +367,7 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   extern __shared__ double ys[];
   // a finished solver skips its remaining products, except the one that
   // still carries its last vector update
-  if (EP && a.done && *a.done && !(a.active && *a.active)) return;
+  if (EP && a.done && glb(a.done)[0] && !(a.active && glb(a.active)[0])) return;
   const int32_t t = xcd_tile(blockIdx.x, a.ntiles);
   if (t >= a.ntiles) return;
   tile_body<V, X, K, EP, GEN>(a, t, ys, s_red);
@@ -362,7 +391,7 @@ __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restric
   for (int32_t it = qbeg[q] + j; it < end; it += J) {
     const int2 w = items[it];
     const prod_task &a = tasks[w.x];
-    if (EP && a.done && *a.done && !(a.active && *a.active)) continue;
+    if (EP && a.done && glb(a.done)[0] && !(a.active && glb(a.active)[0])) continue;
     tile_body<V, X, K, EP, GEN>(a, w.y, ys, s_red);
     __syncthreads();  // ys and s_red are reused by the next item
   }
