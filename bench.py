@@ -160,6 +160,8 @@ def main(argv=None):
     ap.add_argument("--no-mrs", action="store_true", help="skip the MRS time-to-solution runs")
     ap.add_argument("--no-sym", action="store_true", help="skip the symmetric-with-diagonal product")
     ap.add_argument("--no-conflicts", action="store_true", help="skip the conflict-map timing")
+    ap.add_argument("--tile-rows", type=int, default=0, help="tile height of the product (0 = the library default)")
+    ap.add_argument("--w-in", type=int, default=-1, help="inner band half-width (-1 = the paper split, 0)")
     ap.add_argument("--mrs-reps", type=int, default=3, help="timed solves per MRS precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix workload")
     ap.add_argument("--warm-cache", action="store_true",
@@ -201,11 +203,12 @@ def main(argv=None):
     # preprocessing (reported separately, not part of a step)
     mats = []
     t0 = time.perf_counter()
-    mats.append(p3.Matrix(L).reorder(value_dtype=vdt))
+    split = dict(value_dtype=vdt, tile_rows=args.tile_rows, w_in=args.w_in)
+    mats.append(p3.Matrix(L).reorder(**split))
     torch.cuda.synchronize()
     reorder_ms = (time.perf_counter() - t0) * 1e3
     for _ in range(copies - 1):
-        mats.append(p3.Matrix(L).reorder(value_dtype=vdt))
+        mats.append(p3.Matrix(L).reorder(**split))
     info = mats[0].info()
     x0 = torch.from_numpy(synth.vector(n, 1101)).to(dev, tdt)
     xs = [x0.clone() for _ in range(copies)]
@@ -311,7 +314,7 @@ def main(argv=None):
     # the vector precision to the algorithmic bytes
     if not args.no_sym:
         dg = synth.values(n, 1203, "normal")
-        smats = [p3.Matrix(L, diag=dg, symmetric=True).reorder(value_dtype=vdt) for _ in range(copies)]
+        smats = [p3.Matrix(L, diag=dg, symmetric=True).reorder(**split) for _ in range(copies)]
 
         def sstep(s):
             c = s % copies

@@ -8,8 +8,12 @@
 //   outer  d > t_out         -> tile-pair blocks of their own.
 // Rows are cut into tiles of T rows.  Entry (i, j) of part p belongs to block
 // (t, p, u) with t = i / T (row tile) and u = j / T (column tile, u <= t).
-// Entries are sorted by (t, p, u, column, row): the blocks of a row tile are
-// contiguous, and inside a block the entries of one column are contiguous.
+// Entries are sorted by (t, p, u, g, row) with g = (j - i) mod T the block
+// diagonal: the blocks of a row tile are contiguous, and inside a block the
+// entries of one diagonal are contiguous.  Along a diagonal rows and columns
+// are all distinct, so the 64 lanes of a chunk mostly add into 64 different
+// LDS rows on both the row side and the column side (lanes adding into one
+// address are serialised).
 // Each entry stores ((i - t*T) << 16 | (j - u*T)) and its value.  Per row
 // tile: its block range; per column tile: the list of blocks whose column tile
 // it is.  The product reads, per tile, its own blocks (row side) and the
@@ -79,7 +83,7 @@ __device__ __forceinline__ void store_vals(int64_t at, double v, double *f64, fl
 }
 
 // Inner band values go to their diagonal-major slot; block entries get a sort
-// key (t, p, u, column offset, row offset) with the entry index as payload.
+// key (t, p, u, block diagonal, row offset) with the entry index as payload.
 __global__ void k_inner_and_keys(const int32_t *__restrict__ erow, const int32_t *__restrict__ pcol,
                                  const double *__restrict__ pval, const int8_t *__restrict__ part, int64_t nnz,
                                  int32_t n, int32_t T, int lgT, int tbits, const int32_t *__restrict__ kpos,
@@ -98,7 +102,7 @@ __global__ void k_inner_and_keys(const int32_t *__restrict__ erow, const int32_t
   uint64_t key = t;
   key = (key << 1) | (uint64_t)(p - 1);
   key = (key << tbits) | u;
-  key = (key << lgT) | cj;
+  key = (key << lgT) | ((cj - ri) & (uint64_t)(T - 1));
   key = (key << lgT) | ri;
   const int32_t at = kpos[e];
   keys[at] = key;
@@ -121,7 +125,7 @@ __global__ void k_fill_blocks(const uint64_t *__restrict__ keys, const uint32_t 
   const uint64_t k = keys[q];
   const uint32_t e = vals[q];
   const uint32_t T1 = (1u << lgT) - 1u;
-  const uint32_t ri = (uint32_t)(k & T1), cj = (uint32_t)((k >> lgT) & T1);
+  const uint32_t ri = (uint32_t)(k & T1), cj = ((uint32_t)(k >> lgT) + ri) & T1;
   ent_rc[q] = (ri << 16) | cj;
   store_vals(q, pval[e], ef64, ef32, ebf16);
   pos_of[e] = (int32_t)q;
@@ -303,7 +307,7 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
     if (nin) P3_HIP(hipMemsetAsync(L.in_bf16.p, 0, nin * sizeof(uint16_t), s));
   }
 
-  // ---- block entries: sort keys (t, p, u, column, row)
+  // ---- block entries: sort keys (t, p, u, block diagonal, row)
   const int32_t ntiles = (int32_t)cdiv(n, T);
   const int tbits = std::max(1, bits_for((uint64_t)std::max(ntiles - 1, 0)));
   const int key_bits = 2 * tbits + 1 + 2 * lgT;
