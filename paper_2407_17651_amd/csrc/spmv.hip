@@ -606,6 +606,14 @@ static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, co
     P3_TRY(raise_lds(k_batch_product<V, X, K, EP, GEN>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
+  // no more persistent workgroups than can be resident at once: the queues
+  // are split statically, so a workgroup that starts late ends late
+  int per_cu = 0, dev = 0, cus = 0;
+  P3_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_product<V, X, K, EP, GEN>, TB, lds));
+  P3_HIP(hipGetDevice(&dev));
+  P3_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int32_t resident = std::max(8, (per_cu * cus) / 8 * 8);
+  grid = std::min(grid, resident);
   k_batch_product<V, X, K, EP, GEN><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
   P3_LAUNCHED();
   return PARS3_OK;
