@@ -125,7 +125,7 @@ def batched(args, p3, synth, torch, np):
     nnzsum = sum(L.nnz for L in Ls)
     Bb = sum(skew_bytes(L.n, L.nnz, "f32", 8) for L in Ls)
     out = {"workload": "256 skew matrices (2D/3D stencils, RGG deg 16), n log-uniform in [2k, 200k], "
-                       "k = 8 FP32 right-hand sides, one persistent graph-captured launch",
+                       "k = 8 FP32 right-hand sides, one graph-captured launch",
            "sum_n": nsum, "sum_nnz_lower": nnzsum, "tile_rows": t8,
            "tuning_ms": {str(T): [round(a, 4), round(b, 4)] for T, (a, b) in tune.items()},
            "ms_per_launch": round(ms, 4), "gbs": round(Bb / (ms * 1e-3) / 1e9, 1),

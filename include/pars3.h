@@ -352,15 +352,15 @@ pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, dou
                              pars3_mrs_info *info, void *stream);
 
 /* Batches of matrices (independent systems of uneven sizes), each reordered
- * and split with its own configuration, processed together: one persistent
- * launch per product walks a work list of (matrix, tile) items split into 8
- * per-XCD queues of equal estimated cost (matrices largest first, tiles
- * ascending), each queue taken round-robin by the persistent workgroups of
- * its XCD; each launch is captured in a hipGraph and replayed.
+ * and split with its own configuration, processed together: one launch per
+ * product covers a work list of (matrix, tile) items split into 8 per-XCD
+ * queues of equal estimated cost (matrices largest first, tiles ascending),
+ * one workgroup per item, the workgroups of an XCD taking its queue in order;
+ * each launch is captured in a hipGraph and replayed.
  *  pars3_batch_create: m reordered handles (the batch keeps pointers to them;
  *    they must outlive it and must not be re-split while it exists).
- *  pars3_batch_info: number of items, persistent grid size and the 9 queue
- *    boundaries (host outputs, each may be NULL).
+ *  pars3_batch_info: number of items, grid size (8 times the longest queue)
+ *    and the 9 queue boundaries (host outputs, each may be NULL).
  *  pars3_batch_spmv: y_i = shifts[i] x_i + D_i x_i + S_i x_i for every matrix
  *    i (D_i = 0 and S_i skew unless made by pars3_create_sss), with
  *    host arrays x[m], y[m] of device pointers (n_i x k row-major vectors in
@@ -373,7 +373,7 @@ pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, dou
  *  pars3_batch_mrs_solve: MRS for (alphas[i] I + S_i) x_i = b_i for every i
  *    (host arrays of m device pointers to FP64 vectors; x holds x0 on entry),
  *    FP64 iterations (opts->precision must be PARS3_F64; FP64 values
- *    needed), all systems advanced together by one persistent product per
+ *    needed), all systems advanced together by one batched product per
  *    iteration (the previous iteration's vector update fused into it) and one
  *    scalar kernel (systems that have converged are skipped), six iterations
  *    per graph replay, the work list compacted whenever the number of running

@@ -1,13 +1,13 @@
 // Many matrices at once: products with block right-hand sides and MRS solves
 // for a batch of independent shifted skew-symmetric systems, each matrix in
-// its own configuration, all of them in one persistent launch per product.
+// its own configuration, all of them in one launch per product.
 //
 // Work list.  Every (matrix, tile) pair is an item with an estimated cost
 // (the tile's share of the matrix's stored entries plus its rows).  Matrices
 // are taken largest first and their tiles in ascending order (so the two
 // reads of a tile-pair block stay close in time); the sequence is cut into 8
-// contiguous queues of equal cost, one per XCD; the persistent workgroups of
-// XCD q take the items of queue q round-robin (see k_batch_product).
+// contiguous queues of equal cost, one per XCD; the workgroups of XCD q take
+// the items of queue q in order, one each (see k_batch_product).
 //
 // The launch of a product is captured once per set of vector pointers in a
 // hipGraph and replayed.
@@ -209,9 +209,11 @@ static void build_queues(const std::vector<pars3_matrix *> &mats, const int32_t 
   for (int k = 1; k <= 8; k++) qb[k] = std::max(qb[k], qb[k - 1]);
 }
 
-static int32_t persistent_grid(int64_t nitems) {
-  // up to 8 workgroups per CU over 256 CUs, a multiple of 8
-  return (int32_t)std::min<int64_t>(2048, 8 * p3::cdiv(std::max<int64_t>(nitems, 1), 8));
+// one workgroup per item of the longest queue, for each of the 8 queues
+static int32_t queue_grid(const std::vector<int32_t> &qb) {
+  int32_t longest = 1;
+  for (int q = 0; q < 8; q++) longest = std::max(longest, qb[q + 1] - qb[q]);
+  return 8 * longest;
 }
 
 extern "C" pars3_status pars3_batch_create(int32_t m, pars3_matrix *const *mats, pars3_batch **out) {
@@ -241,7 +243,7 @@ extern "C" pars3_status pars3_batch_create(int32_t m, pars3_matrix *const *mats,
   std::vector<int32_t> qb;
   build_queues(B->mats, nullptr, it, qb);
   B->nitems = (int32_t)it.size();
-  B->grid = persistent_grid(B->nitems);
+  B->grid = queue_grid(qb);
   if (B->items.alloc(std::max<size_t>(it.size(), 1)) != hipSuccess || B->qbeg.alloc(9) != hipSuccess || B->tasks.alloc(m) != hipSuccess) {
     (void)hipGetLastError();
     return bad(fail(PARS3_ENOMEM, "batch: device allocation failed"));
@@ -467,7 +469,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   std::vector<int2> hit;
   std::vector<int32_t> hqb;
   build_queues(B->mats, nullptr, hit, hqb);
-  int32_t grid = persistent_grid((int64_t)hit.size());
+  int32_t grid = queue_grid(hqb);
   if (!hit.empty()) P3_HIP(hipMemcpyAsync(ditems.p, hit.data(), hit.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   P3_HIP(hipMemcpyAsync(dqb.p, hqb.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice, s));
   // ||b|| and r0 = b - A x0 (y = alpha x0 + S x0 - b)
@@ -524,7 +526,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
       k_bmrs_settle<<<g1(m), BT, 0, s>>>(dev.p, m);
       for (int32_t i = 0; i < m; i++) use[i] = hd[i].done ? 0 : 1;
       build_queues(B->mats, use.data(), hit, hqb);
-      grid = persistent_grid((int64_t)hit.size());
+      grid = queue_grid(hqb);
       if (!hit.empty() && hipMemcpyAsync(ditems.p, hit.data(), hit.size() * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
         st = fail(PARS3_EHIP, "batch mrs: work list upload failed");
       if (st == PARS3_OK && hipMemcpyAsync(dqb.p, hqb.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
@@ -545,7 +547,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   k_bmrs_settle<<<g1(m), BT, 0, s>>>(dev.p, m);
   P3_LAUNCHED();
   build_queues(B->mats, nullptr, hit, hqb);
-  grid = persistent_grid((int64_t)hit.size());
+  grid = queue_grid(hqb);
   if (!hit.empty()) P3_HIP(hipMemcpyAsync(ditems.p, hit.data(), hit.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   P3_HIP(hipMemcpyAsync(dqb.p, hqb.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice, s));
   P3_TRY(launch_batch(PARS3_F64, 1, true, false, tk.p, ditems.p, dqb.p, grid, B->maxT, s));

@@ -374,11 +374,12 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
 }
 
 // Many matrices in one launch: the (matrix, tile) items are split into 8
-// queues, one per XCD (workgroup b runs on XCD b % 8).  The J = grid / 8
-// persistent workgroups of an XCD take the items of its queue round-robin
-// (workgroup j: items j, j + J, j + 2J, ...); the queues are ordered by cost,
-// so neighbouring items cost about the same and no counter is shared.
-// Items of a matrix whose solver has finished are skipped.
+// queues, one per XCD (workgroup b runs on XCD b % 8), each ordered by
+// matrix and ascending tile.  Workgroup b takes item b / 8 of queue b % 8 (the
+// grid covers the longest queue; workgroups past the end of a shorter one
+// return at once), so each XCD walks its queue in order while the hardware
+// dispatcher starts a new item as soon as any workgroup ends.  Items of a
+// matrix whose solver has finished are skipped.
 template <class V, class X, int K, bool EP, bool GEN>
 __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restrict__ tasks,
                                                       const int2 *__restrict__ items,
@@ -386,15 +387,12 @@ __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restric
   __shared__ double s_red[TB / 64];
   extern __shared__ double ys[];
   const int q = blockIdx.x & 7;
-  const int32_t J = gridDim.x >> 3, j = blockIdx.x >> 3;
-  const int32_t end = qbeg[q + 1];
-  for (int32_t it = qbeg[q] + j; it < end; it += J) {
-    const int2 w = items[it];
-    const prod_task &a = tasks[w.x];
-    if (EP && a.done && glb(a.done)[0] && !(a.active && glb(a.active)[0])) continue;
-    tile_body<V, X, K, EP, GEN>(a, w.y, ys, s_red);
-    __syncthreads();  // ys and s_red are reused by the next item
-  }
+  const int32_t it = qbeg[q] + (int32_t)(blockIdx.x >> 3);
+  if (it >= qbeg[q + 1]) return;
+  const int2 w = items[it];
+  const prod_task &a = tasks[w.x];
+  if (EP && a.done && glb(a.done)[0] && !(a.active && glb(a.active)[0])) return;
+  tile_body<V, X, K, EP, GEN>(a, w.y, ys, s_red);
 }
 
 template <class F>
@@ -606,14 +604,6 @@ static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, co
     P3_TRY(raise_lds(k_batch_product<V, X, K, EP, GEN>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
-  // no more persistent workgroups than can be resident at once: the queues
-  // are split statically, so a workgroup that starts late ends late
-  int per_cu = 0, dev = 0, cus = 0;
-  P3_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_product<V, X, K, EP, GEN>, TB, lds));
-  P3_HIP(hipGetDevice(&dev));
-  P3_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int32_t resident = std::max(8, (per_cu * cus) / 8 * 8);
-  grid = std::min(grid, resident);
   k_batch_product<V, X, K, EP, GEN><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
   P3_LAUNCHED();
   return PARS3_OK;
