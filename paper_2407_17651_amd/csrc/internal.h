@@ -169,8 +169,9 @@ struct layout {
   // block, its own blocks (row side) first, then the blocks of its column
   // list (column side); chunk.x = first entry, chunk.y = other tile << 8 |
   // column side << 7 | (length - 1).  The first CHUNKS_FIXED chunks of tile t
-  // sit at chunk_fix[t * CHUNKS_FIXED + q] (CHUNK_EMPTY in .y past the end),
-  // so the product finds them without a pointer load; the rest are
+  // sit at chunk_fix[t * CHUNKS_FIXED + 8 w + k] for chunk w + 4 k (the 8
+  // chunks of wavefront w side by side; CHUNK_EMPTY in .y past the end), so
+  // the product finds them without a pointer load; the rest are
   // chunk_ovf[ovf_ptr[t] .. ovf_ptr[t+1]).
   dbuf<uint2> chunk_fix, chunk_ovf;
   dbuf<int32_t> ovf_ptr;

@@ -218,16 +218,22 @@ __global__ void k_overflow_count(const int32_t *__restrict__ tch_ptr, int32_t nt
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < ntiles) ocnt[t] = max(0, tch_ptr[t + 1] - tch_ptr[t] - CHUNKS_FIXED);
 }
-// One thread per fixed slot (t, q): slot q < count takes chunk q of tile t,
-// the others the empty marker; slot 0 also moves the tile's overflow chunks.
+// One thread per fixed slot (t, s).  The fixed chunks of a tile are dealt to
+// its 4 wavefronts round-robin (wavefront w takes chunks w, w + 4, ...), and
+// the 8 chunks of one wavefront are stored next to each other, so a
+// wavefront reads its descriptors with one 64-byte scalar load: slot
+// s = 8 w + k holds chunk w + 4 k, or the empty marker past the tile's count.
+// Slot 0 also moves the tile's overflow chunks.
 __global__ void k_chunk_place(const int32_t *__restrict__ tch_ptr, const uint2 *__restrict__ chunk, int32_t ntiles,
                               const int32_t *__restrict__ ovf_ptr, uint2 *__restrict__ fix, uint2 *__restrict__ ovf) {
+  constexpr int WAVES = 4, PER = CHUNKS_FIXED / WAVES;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)ntiles * CHUNKS_FIXED) return;
-  const int32_t t = (int32_t)(g / CHUNKS_FIXED), q = (int32_t)(g % CHUNKS_FIXED);
+  const int32_t t = (int32_t)(g / CHUNKS_FIXED), sl = (int32_t)(g % CHUNKS_FIXED);
+  const int32_t q = (sl % PER) * WAVES + sl / PER;
   const int32_t c0 = tch_ptr[t], cnt = tch_ptr[t + 1] - c0;
   fix[g] = q < cnt ? chunk[c0 + q] : make_uint2(0u, CHUNK_EMPTY);
-  if (q == 0)
+  if (sl == 0)
     for (int32_t c = CHUNKS_FIXED; c < cnt; c++) ovf[ovf_ptr[t] + c - CHUNKS_FIXED] = chunk[c0 + c];
 }
 __global__ void k_pos_prefix(const int8_t *__restrict__ part, int64_t nnz, int32_t *__restrict__ flag) {

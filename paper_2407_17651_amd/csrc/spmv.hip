@@ -133,71 +133,97 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t ntiles) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Loads of one group of chunks (one per q) and their products added into
-// the LDS row sums; a descriptor with .y == CHUNK_EMPTY is skipped.
-// sym: the column side adds l_ij x_i (symmetric S) instead of subtracting it.
-// Every load of the group is issued before any result is used.  Lanes past a
-// chunk's end re-read its last entry (in bounds, the same cache line) and are
-// masked only when their product is added; the only branches around loads
-// test the wave-uniform descriptors.  (A lane-divergent branch around a load
-// whose result is used inside it makes the compiler wait for that load before
-// the next one is issued.)
-template <class V, class X, int K>
-__device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
-                                            gptr<uint32_t> ent_rc, gptr<V> ent_v, gptr<X> x, double *ys) {
+// One group of chunks (one per q) in three phases: the entry loads, then the
+// x gathers, then the products added into the LDS row sums; a descriptor
+// with .y == CHUNK_EMPTY is skipped.  sym: the column side adds l_ij x_i
+// (symmetric S) instead of subtracting it.  Every load of a phase is issued
+// before any result is used.  Lanes past a chunk's end re-read its last entry
+// (in bounds, the same cache line) and are masked only when their product is
+// added; the only branches around loads test the wave-uniform descriptors.
+// (A lane-divergent branch around a load whose result is used inside it
+// makes the compiler wait for that load before the next one is issued.)
+template <class V>
+struct group_entries {
   uint32_t rc[PRE];
   typename vload<V>::R vv[PRE];
+};
+template <class X, int K>
+struct group_gathers {
+  int32_t slot[PRE];
+  X coef[PRE], xv[PRE][K];
+};
+
+template <class V>
+__device__ __forceinline__ void group_load(const uint2 (&d)[PRE], int32_t lane, gptr<uint32_t> ent_rc,
+                                           gptr<V> ent_v, group_entries<V> &g) {
 #pragma unroll
   for (int q = 0; q < PRE; q++) {
-    rc[q] = 0u;
-    vv[q] = 0;
-    if (d[q].y != CHUNK_EMPTY) {
-      const int32_t len = (int32_t)(d[q].y & 127u) + 1;
-      const int64_t e = (int64_t)d[q].x + min(lane, len - 1);
-      // the column side reads a block first and leaves it in L2; the row
-      // side is its last use (nontemporal)
-      if ((d[q].y >> 7) & 1u) {
-        rc[q] = ent_rc[e];
-        vv[q] = vload<V>::ld(ent_v, e);
-      } else {
-        rc[q] = __builtin_nontemporal_load(ent_rc + e);
-        vv[q] = vload<V>::nt(ent_v, e);
-      }
+    g.rc[q] = 0u;
+    g.vv[q] = 0;
+    if (d[q].y == CHUNK_EMPTY) continue;  // wave-uniform: no load at all
+    const int32_t len = (int32_t)(d[q].y & 127u) + 1;
+    const int64_t e = (int64_t)d[q].x + min(lane, len - 1);
+    // the column side reads a block first and leaves it in L2; the row side
+    // is its last use (nontemporal)
+    if ((d[q].y >> 7) & 1u) {
+      g.rc[q] = ent_rc[e];
+      g.vv[q] = vload<V>::ld(ent_v, e);
+    } else {
+      g.rc[q] = __builtin_nontemporal_load(ent_rc + e);
+      g.vv[q] = vload<V>::nt(ent_v, e);
     }
   }
-  int32_t slot[PRE], xrow[PRE];
-  X coef[PRE], xv[PRE][K];
+}
+
+template <class V, class X, int K>
+__device__ __forceinline__ void group_gather(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
+                                             const group_entries<V> &g, gptr<X> x, group_gathers<X, K> &h) {
+  int32_t xrow[PRE];
 #pragma unroll
   for (int q = 0; q < PRE; q++) {
-    slot[q] = -1;
+    h.slot[q] = -1;
     xrow[q] = 0;
-    coef[q] = (X)0;
+    h.coef[q] = (X)0;
     if (d[q].y != CHUNK_EMPTY) {
       const int32_t len = (int32_t)(d[q].y & 127u) + 1;
       const bool col_side = (d[q].y >> 7) & 1u;
       const int32_t other = (int32_t)(d[q].y >> 8);
-      const int32_t ri = (int32_t)(rc[q] >> 16), cj = (int32_t)(rc[q] & 0xffffu);
-      const X val = vload<V>::template cvt<X>(vv[q]);
-      slot[q] = lane < len ? (col_side ? cj : ri) : -1;
+      const int32_t ri = (int32_t)(g.rc[q] >> 16), cj = (int32_t)(g.rc[q] & 0xffffu);
+      const X val = vload<V>::template cvt<X>(g.vv[q]);
+      h.slot[q] = lane < len ? (col_side ? cj : ri) : -1;
       xrow[q] = (other << lgT) + (col_side ? ri : cj);
-      coef[q] = col_side && !sym ? -val : val;
+      h.coef[q] = col_side && !sym ? -val : val;
     }
   }
 #pragma unroll
   for (int q = 0; q < PRE; q++) {
-    if (d[q].y != CHUNK_EMPTY) {
-      rowvec<X, K>::load(x, xrow[q], xv[q]);
-    } else {
+    if (d[q].y == CHUNK_EMPTY) {
 #pragma unroll
-      for (int c = 0; c < K; c++) xv[q][c] = (X)0;
+      for (int c = 0; c < K; c++) h.xv[q][c] = (X)0;
+    } else {
+      rowvec<X, K>::load(x, xrow[q], h.xv[q]);
     }
   }
+}
+
+template <class X, int K>
+__device__ __forceinline__ void group_add(const group_gathers<X, K> &h, double *ys) {
 #pragma unroll
   for (int q = 0; q < PRE; q++)
-    if (slot[q] >= 0) {
+    if (h.slot[q] >= 0) {
 #pragma unroll
-      for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * KP<K> + c], (double)(coef[q] * xv[q][c]));
+      for (int c = 0; c < K; c++) atomicAdd(&ys[h.slot[q] * KP<K> + c], (double)(h.coef[q] * h.xv[q][c]));
     }
+}
+
+template <class V, class X, int K>
+__device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
+                                            gptr<uint32_t> ent_rc, gptr<V> ent_v, gptr<X> x, double *ys) {
+  group_entries<V> g;
+  group_load<V>(d, lane, ent_rc, ent_v, g);
+  group_gathers<X, K> h;
+  group_gather<V, X, K>(d, lane, lgT, sym, g, x, h);
+  group_add<X, K>(h, ys);
 }
 
 // Output phase of a tile (after its LDS row sums are complete): y = (shift
@@ -232,7 +258,7 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
     }
   }
   double sq = 0.0;
-  for (int32_t r = threadIdx.x; r < rows; r += TB) {
+  for (int32_t r = threadIdx.x, rr = 0; r < rows; r += TB, rr++) {
     const int64_t i = r0 + r;
     X acc[K];
 #pragma unroll
@@ -273,7 +299,7 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
     const X sh = dg ? shift + dg[i] : shift;
 #pragma unroll
     for (int c = 0; c < K; c++) {
-      const X xi = r == (int32_t)threadIdx.x ? xown[c] : x[i * K + c];
+      const X xi = rr == 0 ? xown[c] : x[i * K + c];
       acc[c] = EP ? sh * xi + sc * acc[c] : sh * xi + acc[c];
     }
     if (EP && z) {
@@ -334,15 +360,12 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   // thread's first own row are requested before anything else
   uint2 d[PRE];
 #pragma unroll
-  for (int q = 0; q < PRE; q++) d[q] = load_desc(a.chunk_fix, (int64_t)t * CHUNKS_FIXED + wave + q * (TB / 64));
+  for (int q = 0; q < PRE; q++) d[q] = load_desc(a.chunk_fix, (int64_t)t * CHUNKS_FIXED + wave * PRE + q);
   const int32_t o0 = glb(a.ovf_ptr)[t], o1 = glb(a.ovf_ptr)[t + 1];
+  // own x row, clamped into the matrix (a thread past the last row keeps a
+  // value it never uses) so that no branch surrounds the load
   X xown[K];
-  if ((int32_t)threadIdx.x < rows) {
-    rowvec<X, K>::load(x, (int64_t)r0 + threadIdx.x, xown);
-  } else {
-#pragma unroll
-    for (int c = 0; c < K; c++) xown[c] = (X)0;
-  }
+  rowvec<X, K>::load(x, min((int64_t)r0 + threadIdx.x, (int64_t)n - 1), xown);
   for (int32_t s = threadIdx.x; s < rows * KP<K>; s += TB) ys[s] = 0.0;
   __syncthreads();
   chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
@@ -350,7 +373,10 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
 #pragma unroll
     for (int q = 0; q < PRE; q++) {
       const int32_t c = cb + q * (TB / 64);
-      d[q] = c < o1 ? load_desc(a.chunk_ovf, c) : make_uint2(0u, CHUNK_EMPTY);
+      // past the end: a re-read of the last descriptor, marked empty (no
+      // branch around the load, which would make the compiler wait for it)
+      d[q] = load_desc(a.chunk_ovf, min(c, o1 - 1));
+      if (c >= o1) d[q].y = CHUNK_EMPTY;
     }
     chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
   }
@@ -372,6 +398,7 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   if (t >= a.ntiles) return;
   tile_body<V, X, K, EP, GEN>(a, t, ys, s_red);
 }
+
 
 // Many matrices in one launch: the (matrix, tile) items are split into 8
 // queues, one per XCD (workgroup b runs on XCD b % 8), each ordered by
