@@ -356,19 +356,26 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   const int32_t rows = min(T, n - r0);
   const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x >> 6);
   const int32_t lane = threadIdx.x & 63;
-  // descriptors of the first group, the overflow range and x of the
-  // thread's first own row are requested before anything else
+  // descriptors of the first group, the overflow range, the first group's
+  // entries and x of the thread's first own row are requested before the
+  // LDS row sums are cleared
   uint2 d[PRE];
 #pragma unroll
   for (int q = 0; q < PRE; q++) d[q] = load_desc(a.chunk_fix, (int64_t)t * CHUNKS_FIXED + wave * PRE + q);
   const int32_t o0 = glb(a.ovf_ptr)[t], o1 = glb(a.ovf_ptr)[t + 1];
+  group_entries<V> g;
+  group_load<V>(d, lane, ent_rc, ent_v, g);
   // own x row, clamped into the matrix (a thread past the last row keeps a
   // value it never uses) so that no branch surrounds the load
   X xown[K];
   rowvec<X, K>::load(x, min((int64_t)r0 + threadIdx.x, (int64_t)n - 1), xown);
   for (int32_t s = threadIdx.x; s < rows * KP<K>; s += TB) ys[s] = 0.0;
   __syncthreads();
-  chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
+  {
+    group_gathers<X, K> h;
+    group_gather<V, X, K>(d, lane, lgT, GEN && a.sym != 0, g, x, h);
+    group_add<X, K>(h, ys);
+  }
   for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
 #pragma unroll
     for (int q = 0; q < PRE; q++) {
@@ -378,6 +385,9 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
       d[q] = load_desc(a.chunk_ovf, min(c, o1 - 1));
       if (c >= o1) d[q].y = CHUNK_EMPTY;
     }
+    // all 8 descriptor loads go out before the first entry load (left to
+    // itself the scheduler interleaves them and waits once per chunk)
+    __builtin_amdgcn_sched_barrier(0);
     chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
   }
   __syncthreads();
