@@ -30,9 +30,13 @@ METRIC = "skew-SpMV GB/s (% HBM peak) vs full-CSR GPU SpMV; MRS time to 1e-10 re
 SIZES = {"f64": (8, 8), "f32": (4, 4), "bf16": (2, 4)}  # (value bytes, vector bytes)
 
 
-def kernel_name(dtype):
+def kernel_name(dtype, tile_rows=256):
+    """Name of the product kernel the bench times: value and vector types, one
+    right-hand side, no solver epilogue, skew kind, and the entry word type
+    (16-bit for tiles of at most 256 rows)."""
     v, x = {"f64": ("double", "double"), "f32": ("float", "float"), "bf16": ("unsigned short", "float")}[dtype]
-    return f"p3::k_tile_product<{v}, {x}, 1, false, false>"
+    e = "unsigned short" if tile_rows <= 256 else "unsigned int"
+    return f"p3::k_tile_product<{v}, {x}, 1, false, false, {e}>"
 
 
 def source_hash():
@@ -45,11 +49,14 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(dtype):
+def measured_traffic(dtype, tile_rows=256, w_in=0):
     """HBM bytes per launch of the product kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
-    or None when there is none for this precision or the kernel sources
-    changed since it was taken."""
+    or None when there is none for this precision, the layout differs from
+    the one it was taken on (256-row tiles, no inner band), or the kernel
+    sources changed since it was taken."""
+    if tile_rows != 256 or w_in != 0:
+        return None
     path = os.path.join(ROOT, "profiles", f"k_tile_product_3d128_{dtype}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -187,7 +194,6 @@ def main(argv=None):
     vec = p3.F64 if args.dtype == "f64" else p3.F32
     tdt = torch.float64 if vec == p3.F64 else torch.float32
     B = skew_bytes(n, nnz, args.dtype)
-    KERNEL = kernel_name(args.dtype)
     copies = args.copies or max(1, math.ceil(768e6 / B))
     print(f"[bench] workload 3D 128^3 n={n} nnz_L={nnz} dtype={args.dtype} copies={copies}", file=sys.stderr,
           flush=True)
@@ -210,6 +216,7 @@ def main(argv=None):
     for _ in range(copies - 1):
         mats.append(p3.Matrix(L).reorder(**split))
     info = mats[0].info()
+    KERNEL = kernel_name(args.dtype, info["tile_rows"])
     x0 = torch.from_numpy(synth.vector(n, 1101)).to(dev, tdt)
     xs = [x0.clone() for _ in range(copies)]
     ys = [torch.empty_like(x0) for _ in range(copies)]
@@ -246,6 +253,7 @@ def main(argv=None):
     # the timed region's average is that kernel's average launch duration
     t_band = ms
     achieved = B / (t_band * 1e-3) / 1e9
+    traffic = measured_traffic(args.dtype, info["tile_rows"], info["w_in"])
 
     out = {
         "metric": METRIC,
@@ -278,8 +286,12 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": measured_traffic(args.dtype),
+            "traffic": traffic,
         },
+        # HBM bytes the counters saw per launch over the launch time (the
+        # layout stores 16-bit entry words, so this is below the algorithmic
+        # count, which charges 4 bytes per index)
+        "measured_hbm_gbs": round(traffic / (t_band * 1e-3) / 1e9, 2) if traffic else None,
     }
 
     # full-CSR GPU products of the same matrix (both triangles stored), same

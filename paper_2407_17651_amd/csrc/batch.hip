@@ -25,7 +25,8 @@ struct pars3_batch {
   std::vector<pars3_matrix *> mats;
   std::vector<int64_t> off;    // vector offsets (prefix of n)
   std::vector<int32_t> poff;   // partial-sum offsets (prefix of tiles)
-  int32_t maxT = 64, grid = 0, nitems = 0;
+  std::vector<int32_t> Ts;     // tile height of each matrix when the batch was made
+  int32_t minT = 1024, maxT = 64, grid = 0, nitems = 0;
   p3::dbuf<int2> items;
   p3::dbuf<int32_t> qbeg;
   hipStream_t gs = nullptr;  // capture stream
@@ -234,9 +235,12 @@ extern "C" pars3_status pars3_batch_create(int32_t m, pars3_matrix *const *mats,
   B->mats.assign(mats, mats + m);
   B->off.assign(m + 1, 0);
   B->poff.assign(m + 1, 0);
+  B->Ts.assign(m, 0);
   for (int32_t i = 0; i < m; i++) {
     B->off[i + 1] = B->off[i] + mats[i]->n;
     B->poff[i + 1] = B->poff[i] + mats[i]->lay.ntiles;
+    B->Ts[i] = mats[i]->lay.T;
+    B->minT = std::min(B->minT, mats[i]->lay.T);
     B->maxT = std::max(B->maxT, mats[i]->lay.T);
   }
   std::vector<int2> it;
@@ -268,12 +272,25 @@ extern "C" pars3_status pars3_batch_info(const pars3_batch *B, int32_t *n_items,
   return PARS3_OK;
 }
 
+// The work list, LDS size and entry word types of a batch were fixed from the
+// layouts its matrices had when it was made.
+static pars3_status check_layouts(const pars3_batch *B) {
+  using namespace p3;
+  for (size_t i = 0; i < B->mats.size(); i++) {
+    const layout &L = B->mats[i]->lay;
+    if (L.T != B->Ts[i] || L.ntiles != B->poff[i + 1] - B->poff[i])
+      return fail(PARS3_ESTATE, "batch: matrix %d was split again after the batch was made", (int)i);
+  }
+  return PARS3_OK;
+}
+
 static pars3_status batch_tasks(pars3_batch *B, const double *shifts, const void *const *x, void *const *y,
                                 int32_t vec_dtype, int32_t value_dtype, std::vector<p3::prod_task> &t, int *vkind) {
   using namespace p3;
   const int32_t m = (int32_t)B->mats.size();
   t.resize(m);
   int vk0 = -1;
+  P3_TRY(check_layouts(B));
   for (int32_t i = 0; i < m; i++) {
     int vk = -1;
     P3_TRY(make_task(B->mats[i], vec_dtype, value_dtype, &t[i], &vk));
@@ -320,7 +337,8 @@ extern "C" pars3_status pars3_batch_spmv(pars3_batch *B, const double *shifts, c
     P3_HIP(hipStreamBeginCapture(B->gs, hipStreamCaptureModeThreadLocal));
     bool gen = false;
     for (const pars3_matrix *A : B->mats) gen = gen || is_general(A);
-    pars3_status st = launch_batch(vk, k, false, gen, B->tasks.p, B->items.p, B->qbeg.p, B->grid, B->maxT, B->gs);
+    pars3_status st =
+        launch_batch(vk, k, false, gen, B->tasks.p, B->items.p, B->qbeg.p, B->grid, B->minT, B->maxT, B->gs);
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(B->gs, &g);
     if (st != PARS3_OK) {
@@ -435,6 +453,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   // update on the same rows
   std::vector<prod_task> ht(7 * (size_t)m);
   int vk = -1;
+  P3_TRY(check_layouts(B));
   for (int32_t i = 0; i < m; i++) {
     const int64_t e = B->off[i];
     for (int r = 0; r < 7; r++) {
@@ -476,7 +495,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   k_bmrs_const<<<g1(m), BT, 0, s>>>(dev.p, m);
   k_bnorm<<<m, BT, 0, s>>>(Bv.p, doff.p, nb2.p);
   P3_LAUNCHED();
-  P3_TRY(launch_batch(PARS3_F64, 1, true, false, tk.p, ditems.p, dqb.p, grid, B->maxT, s));
+  P3_TRY(launch_batch(PARS3_F64, 1, true, false, tk.p, ditems.p, dqb.p, grid, B->minT, B->maxT, s));
   k_bnorm<<<m, BT, 0, s>>>(Y.p, doff.p, nr2.p);
   k_bmrs_init<<<g1(m), BT, 0, s>>>(P, nb2.p, nr2.p, alph.p, o.tol, o.maxit, m);
   if (nvb) k_bmrs_start<<<nvb, BT, 0, s>>>(P);
@@ -493,7 +512,8 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
     P3_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     pars3_status st2 = PARS3_OK;
     for (int J = 1; J <= 6 && st2 == PARS3_OK; J++) {
-      st2 = launch_batch(PARS3_F64, 1, true, false, tk.p + (size_t)J * m, ditems.p, dqb.p, grid, B->maxT, s);
+      st2 = launch_batch(PARS3_F64, 1, true, false, tk.p + (size_t)J * m, ditems.p, dqb.p, grid, B->minT, B->maxT,
+                         s);
       if (st2 == PARS3_OK) k_bmrs_scalar<<<m, 1024, 0, s>>>(P, (J - 1) & 1);
     }
     const hipError_t ee = hipStreamEndCapture(s, &graph);
@@ -550,7 +570,7 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   grid = queue_grid(hqb);
   if (!hit.empty()) P3_HIP(hipMemcpyAsync(ditems.p, hit.data(), hit.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   P3_HIP(hipMemcpyAsync(dqb.p, hqb.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  P3_TRY(launch_batch(PARS3_F64, 1, true, false, tk.p, ditems.p, dqb.p, grid, B->maxT, s));
+  P3_TRY(launch_batch(PARS3_F64, 1, true, false, tk.p, ditems.p, dqb.p, grid, B->minT, B->maxT, s));
   k_bnorm<<<m, BT, 0, s>>>(Y.p, doff.p, nr2.p);
   P3_LAUNCHED();
   std::vector<double> hr(m), hb(m);

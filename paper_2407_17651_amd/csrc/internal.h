@@ -144,6 +144,7 @@ pars3_status iota_i32(int32_t *p, int64_t m, hipStream_t s);
 // ---------------------------------------------------------------- stored layouts
 constexpr int CHUNKS_FIXED = 32;          // fixed chunk slots per tile (4 wavefronts x 8)
 constexpr uint32_t CHUNK_EMPTY = 0xffffffffu;
+constexpr int ENT16_MAX_LGT = 8;          // tiles of at most 256 rows store 16-bit entry words
 // One SpMV layout: the three parts of the split arranged for the kernel.
 struct layout {
   int32_t T = 256, lgT = 8, w_in = 0, t_out = 0;
@@ -155,8 +156,11 @@ struct layout {
   dbuf<float> in_f32;
   dbuf<uint16_t> in_bf16;
   // tile-pair blocks: entries [blk_start[b], blk_start[b+1]) of block b, whose
-  // row tile is blk_t[b] and column tile blk_u[b]; entry word
-  // (row - row tile start) << 16 | (column - column tile start)
+  // row tile is blk_t[b] and column tile blk_u[b].  Entry word: the row's and
+  // the column's offsets in their tiles, (row offset) << 8 | column offset in
+  // 16 bits when T <= 256 (ent_rc16), << 16 in 32 bits otherwise (ent_rc);
+  // only one of the two is allocated
+  dbuf<uint16_t> ent_rc16;
   dbuf<uint32_t> ent_rc;
   dbuf<double> ent_f64;
   dbuf<float> ent_f32;
@@ -341,7 +345,7 @@ struct prod_task {
   const uint2 *chunk_fix;
   const int32_t *ovf_ptr;
   const uint2 *chunk_ovf;
-  const uint32_t *ent_rc;
+  const void *ent_rc;  // entry words: uint16_t when lgT <= ENT16_MAX_LGT, uint32_t otherwise
   const void *ent_v, *dia;
   int32_t w_in, ntiles, lgT, n;
   int32_t sym;       // 1: S = L + L^T (the transposed update keeps its sign)
@@ -364,12 +368,13 @@ struct prod_task {
 // vec_dtype (value_dtype picks FP32 or BF16 values when both are stored, -1:
 // whichever is stored); *vkind receives the value type used.
 pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, prod_task *a, int *vkind);
-// Persistent product over many tasks: items (task, tile) in 8 queues
-// [qbeg[q], qbeg[q+1]), one per XCD, taken round-robin.  maxT: the largest
-// tile height among the tasks.  ep: with the solver epilogue (k = 1 only).
-// gen: some task is symmetric or has a diagonal array.
+// Product over many tasks, one workgroup per item: items (task, tile) in 8
+// queues [qbeg[q], qbeg[q+1]), one per XCD; grid = 8 x the longest queue.
+// minT, maxT: the smallest and largest tile heights among the tasks (they
+// decide the LDS size and the entry word types).  ep: with the solver
+// epilogue (k = 1 only).  gen: some task is symmetric or has a diagonal array.
 pars3_status launch_batch(int vkind, int k, bool ep, bool gen, const prod_task *tasks, const int2 *items,
-                          const int32_t *qbeg, int32_t grid, int32_t maxT, hipStream_t s);
+                          const int32_t *qbeg, int32_t grid, int32_t minT, int32_t maxT, hipStream_t s);
 // skewform.hip: MRS for alpha*I + D + S through its shifted skew form
 pars3_status mrs_shifted(pars3_matrix *A, double alpha, const double *b, double *x, const pars3_mrs_opts &o,
                          pars3_mrs_info *info, hipStream_t s);

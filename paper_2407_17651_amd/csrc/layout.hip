@@ -116,8 +116,9 @@ __global__ void k_block_flags(const uint64_t *__restrict__ keys, int64_t m, int 
 }
 __global__ void k_fill_blocks(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t m, int lgT,
                               int tbits, const int32_t *__restrict__ flag, const int32_t *__restrict__ bpos,
-                              const double *__restrict__ pval, uint32_t *__restrict__ ent_rc, double *ef64, float *ef32,
-                              uint16_t *ebf16, int32_t *__restrict__ pos_of, int32_t *__restrict__ blk_start,
+                              const double *__restrict__ pval, uint32_t *ent32, uint16_t *ent16, double *ef64,
+                              float *ef32, uint16_t *ebf16, int32_t *__restrict__ pos_of,
+                              int32_t *__restrict__ blk_start,
                               int32_t *__restrict__ blk_t, int32_t *__restrict__ blk_u,
                               int32_t *__restrict__ tcount, int32_t *__restrict__ ucount) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -126,7 +127,8 @@ __global__ void k_fill_blocks(const uint64_t *__restrict__ keys, const uint32_t 
   const uint32_t e = vals[q];
   const uint32_t T1 = (1u << lgT) - 1u;
   const uint32_t ri = (uint32_t)(k & T1), cj = ((uint32_t)(k >> lgT) + ri) & T1;
-  ent_rc[q] = (ri << 16) | cj;
+  if (ent16) ent16[q] = (uint16_t)((ri << 8) | cj);
+  else ent32[q] = (ri << 16) | cj;
   store_vals(q, pval[e], ef64, ef32, ebf16);
   pos_of[e] = (int32_t)q;
   if (flag[q]) {
@@ -359,7 +361,11 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   P3_HIP(hipMemcpyAsync(&nb, bpos.p + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   P3_HIP(hipStreamSynchronize(s));
   const int32_t m32 = (int32_t)m;
-  P3_HIP(L.ent_rc.alloc(m));
+  const bool e16 = lgT <= ENT16_MAX_LGT;
+  L.ent_rc.release();
+  L.ent_rc16.release();
+  if (e16) P3_HIP(L.ent_rc16.alloc(m));
+  else P3_HIP(L.ent_rc.alloc(m));
   P3_HIP(L.pos_of.alloc(nnz));
   P3_HIP(L.blk_start.alloc(nb + 1));
   P3_HIP(L.blk_t.alloc(nb));
@@ -375,9 +381,9 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   if (nnz > 0) P3_TRY(fill_i32(L.pos_of.p, -1, nnz, s));
   if (m > 0) {
     k_fill_blocks<<<nblk(m), TB, 0, s>>>(k0.p, v0.p, m, lgT, tbits, bflag.p, bpos.p, A->pval.p, L.ent_rc.p,
-                                         want64 ? L.ent_f64.p : nullptr, want32 ? L.ent_f32.p : nullptr,
-                                         want16 ? L.ent_bf16.p : nullptr, L.pos_of.p, L.blk_start.p, L.blk_t.p,
-                                         L.blk_u.p, tcount.p, ucount.p);
+                                         L.ent_rc16.p, want64 ? L.ent_f64.p : nullptr,
+                                         want32 ? L.ent_f32.p : nullptr, want16 ? L.ent_bf16.p : nullptr, L.pos_of.p,
+                                         L.blk_start.p, L.blk_t.p, L.blk_u.p, tcount.p, ucount.p);
     P3_LAUNCHED();
   }
   P3_TRY(scan_i32(tcount.p, L.tblk_ptr.p, ntiles, s));

@@ -87,6 +87,25 @@ struct vload {
   }
 };
 
+// Entry words (row offset in its tile) << SH | (column offset in its tile):
+// 16-bit words with SH = 8 for tiles of at most 256 rows, 32-bit words with
+// SH = 16 for taller ones.  Loads return the word zero-extended in a full
+// register (one load per register: the compiler keeps the same load and wait
+// order for both widths, so no barrier is needed here; one measured 11 more
+// registers and slower solver epilogues).
+template <class E>
+struct eword {
+  static constexpr int SH = sizeof(E) == 2 ? 8 : 16;
+  static __device__ __forceinline__ uint32_t ld(gptr<E> p, int64_t i) { return (uint32_t)p[i]; }
+  static __device__ __forceinline__ uint32_t nt(gptr<E> p, int64_t i) {
+    return (uint32_t)__builtin_nontemporal_load(p + i);
+  }
+  static __device__ __forceinline__ void decode(uint32_t w, int32_t &ri, int32_t &cj) {
+    ri = (int32_t)(w >> SH);
+    cj = (int32_t)(w & ((1u << SH) - 1u));
+  }
+};
+
 // The k values of one row of x (or y) as 16-byte vector accesses where the
 // row is a whole number of them (rows of k >= 2 values are 16-byte aligned:
 // the library requires 16-byte aligned vectors when k >= 2).
@@ -153,9 +172,9 @@ struct group_gathers {
   X coef[PRE], xv[PRE][K];
 };
 
-template <class V>
-__device__ __forceinline__ void group_load(const uint2 (&d)[PRE], int32_t lane, gptr<uint32_t> ent_rc,
-                                           gptr<V> ent_v, group_entries<V> &g) {
+template <class V, class E>
+__device__ __forceinline__ void group_load(const uint2 (&d)[PRE], int32_t lane, gptr<E> ent_rc, gptr<V> ent_v,
+                                           group_entries<V> &g) {
 #pragma unroll
   for (int q = 0; q < PRE; q++) {
     g.rc[q] = 0u;
@@ -166,16 +185,16 @@ __device__ __forceinline__ void group_load(const uint2 (&d)[PRE], int32_t lane, 
     // the column side reads a block first and leaves it in L2; the row side
     // is its last use (nontemporal)
     if ((d[q].y >> 7) & 1u) {
-      g.rc[q] = ent_rc[e];
+      g.rc[q] = eword<E>::ld(ent_rc, e);
       g.vv[q] = vload<V>::ld(ent_v, e);
     } else {
-      g.rc[q] = __builtin_nontemporal_load(ent_rc + e);
+      g.rc[q] = eword<E>::nt(ent_rc, e);
       g.vv[q] = vload<V>::nt(ent_v, e);
     }
   }
 }
 
-template <class V, class X, int K>
+template <class V, class X, int K, class E>
 __device__ __forceinline__ void group_gather(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
                                              const group_entries<V> &g, gptr<X> x, group_gathers<X, K> &h) {
   int32_t xrow[PRE];
@@ -188,7 +207,8 @@ __device__ __forceinline__ void group_gather(const uint2 (&d)[PRE], int32_t lane
       const int32_t len = (int32_t)(d[q].y & 127u) + 1;
       const bool col_side = (d[q].y >> 7) & 1u;
       const int32_t other = (int32_t)(d[q].y >> 8);
-      const int32_t ri = (int32_t)(g.rc[q] >> 16), cj = (int32_t)(g.rc[q] & 0xffffu);
+      int32_t ri, cj;
+      eword<E>::decode(g.rc[q], ri, cj);
       const X val = vload<V>::template cvt<X>(g.vv[q]);
       h.slot[q] = lane < len ? (col_side ? cj : ri) : -1;
       xrow[q] = (other << lgT) + (col_side ? ri : cj);
@@ -216,13 +236,13 @@ __device__ __forceinline__ void group_add(const group_gathers<X, K> &h, double *
     }
 }
 
-template <class V, class X, int K>
+template <class V, class X, int K, class E>
 __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
-                                            gptr<uint32_t> ent_rc, gptr<V> ent_v, gptr<X> x, double *ys) {
+                                            gptr<E> ent_rc, gptr<V> ent_v, gptr<X> x, double *ys) {
   group_entries<V> g;
-  group_load<V>(d, lane, ent_rc, ent_v, g);
+  group_load<V, E>(d, lane, ent_rc, ent_v, g);
   group_gathers<X, K> h;
-  group_gather<V, X, K>(d, lane, lgT, sym, g, x, h);
+  group_gather<V, X, K, E>(d, lane, lgT, sym, g, x, h);
   group_add<X, K>(h, ys);
 }
 
@@ -344,11 +364,12 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
 // faster than of FP32 here.  Called by every thread of the workgroup.  EP:
 // the solver epilogue (y += beta z, per-tile sums of y^2) is compiled in.
 // GEN: the task's kind (symmetric or skew) and diagonal array are honoured;
-// without it the product is the skew one with the scalar shift only.
-template <class V, class X, int K, bool EP, bool GEN>
+// without it the product is the skew one with the scalar shift only.  E:
+// the type of the entry words (uint16_t for tiles of at most 256 rows).
+template <class V, class X, int K, bool EP, bool GEN, class E>
 __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double *ys, double *s_red) {
   gptr<V> ent_v = glb((const V *)a.ent_v);
-  gptr<uint32_t> ent_rc = glb(a.ent_rc);
+  gptr<E> ent_rc = glb((const E *)a.ent_rc);
   gptr<X> x = glb((const X *)a.x);
   const int32_t n = a.n, lgT = a.lgT;
   const int32_t T = 1 << lgT;
@@ -364,7 +385,7 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   for (int q = 0; q < PRE; q++) d[q] = load_desc(a.chunk_fix, (int64_t)t * CHUNKS_FIXED + wave * PRE + q);
   const int32_t o0 = glb(a.ovf_ptr)[t], o1 = glb(a.ovf_ptr)[t + 1];
   group_entries<V> g;
-  group_load<V>(d, lane, ent_rc, ent_v, g);
+  group_load<V, E>(d, lane, ent_rc, ent_v, g);
   // own x row, clamped into the matrix (a thread past the last row keeps a
   // value it never uses) so that no branch surrounds the load
   X xown[K];
@@ -373,7 +394,7 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   __syncthreads();
   {
     group_gathers<X, K> h;
-    group_gather<V, X, K>(d, lane, lgT, GEN && a.sym != 0, g, x, h);
+    group_gather<V, X, K, E>(d, lane, lgT, GEN && a.sym != 0, g, x, h);
     group_add<X, K>(h, ys);
   }
   for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
@@ -388,7 +409,7 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
     // all 8 descriptor loads go out before the first entry load (left to
     // itself the scheduler interleaves them and waits once per chunk)
     __builtin_amdgcn_sched_barrier(0);
-    chunk_group<V, X, K>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
+    chunk_group<V, X, K, E>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
   }
   __syncthreads();
   tile_final<V, X, K, EP, GEN>(a, t, xown, ys, s_red);
@@ -396,8 +417,8 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
 
 // One matrix: one workgroup per tile.  EP: with the solver epilogue (a
 // finished solver's done flag skips the whole launch).  GEN: symmetric kind
-// and diagonal array.
-template <class V, class X, int K, bool EP, bool GEN>
+// and diagonal array.  E: the entry word type of the layout's tile height.
+template <class V, class X, int K, bool EP, bool GEN, class E>
 __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   __shared__ double s_red[TB / 64];
   extern __shared__ double ys[];
@@ -406,7 +427,7 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   if (EP && a.done && glb(a.done)[0] && !(a.active && glb(a.active)[0])) return;
   const int32_t t = xcd_tile(blockIdx.x, a.ntiles);
   if (t >= a.ntiles) return;
-  tile_body<V, X, K, EP, GEN>(a, t, ys, s_red);
+  tile_body<V, X, K, EP, GEN, E>(a, t, ys, s_red);
 }
 
 
@@ -416,8 +437,11 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
 // grid covers the longest queue; workgroups past the end of a shorter one
 // return at once), so each XCD walks its queue in order while the hardware
 // dispatcher starts a new item as soon as any workgroup ends.  Items of a
-// matrix whose solver has finished are skipped.
-template <class V, class X, int K, bool EP, bool GEN>
+// matrix whose solver has finished are skipped.  EW: the entry word size of
+// every task (2 or 4 bytes), or 0 when the tasks mix tile heights on both
+// sides of 256 rows and each item picks its type (a branch uniform over the
+// workgroup).
+template <class V, class X, int K, bool EP, bool GEN, int EW>
 __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restrict__ tasks,
                                                       const int2 *__restrict__ items,
                                                       const int32_t *__restrict__ qbeg) {
@@ -429,7 +453,14 @@ __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restric
   const int2 w = items[it];
   const prod_task &a = tasks[w.x];
   if (EP && a.done && glb(a.done)[0] && !(a.active && glb(a.active)[0])) return;
-  tile_body<V, X, K, EP, GEN>(a, w.y, ys, s_red);
+  if constexpr (EW == 2) {
+    tile_body<V, X, K, EP, GEN, uint16_t>(a, w.y, ys, s_red);
+  } else if constexpr (EW == 4) {
+    tile_body<V, X, K, EP, GEN, uint32_t>(a, w.y, ys, s_red);
+  } else {
+    if (a.lgT <= ENT16_MAX_LGT) tile_body<V, X, K, EP, GEN, uint16_t>(a, w.y, ys, s_red);
+    else tile_body<V, X, K, EP, GEN, uint32_t>(a, w.y, ys, s_red);
+  }
 }
 
 template <class F>
@@ -439,23 +470,23 @@ static pars3_status raise_lds(F *kernel, size_t lds) {
   return PARS3_OK;
 }
 
-template <class V, class X, int K, bool EP, bool GEN>
-static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shift, const X *x, X *y, hipStream_t s,
-                           const epilogue<X> &ep) {
+template <class V, class X, int K, bool EP, bool GEN, class E>
+static pars3_status launch_e(pars3_matrix *A, const V *in_v, const V *ent_v, X shift, const X *x, X *y,
+                             hipStream_t s, const epilogue<X> &ep) {
   const layout &L = A->lay;
   const int32_t n = (int32_t)A->n;
   if (n == 0) return PARS3_OK;
   const size_t lds = (size_t)L.T * KP<K> * sizeof(double);
   static bool raised = false;  // above the default dynamic LDS limit: ask for exactly what is needed
   if (!raised && lds + sizeof(double) * (TB / 64) > LDS_DEFAULT) {
-    P3_TRY(raise_lds(k_tile_product<V, X, K, EP, GEN>, (size_t)1024 * KP<K> * sizeof(double)));
+    P3_TRY(raise_lds(k_tile_product<V, X, K, EP, GEN, E>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
   prod_task a{};
   a.chunk_fix = L.chunk_fix.p;
   a.ovf_ptr = L.ovf_ptr.p;
   a.chunk_ovf = L.chunk_ovf.p;
-  a.ent_rc = L.ent_rc.p;
+  a.ent_rc = sizeof(E) == 2 ? (const void *)L.ent_rc16.p : (const void *)L.ent_rc.p;
   a.ent_v = ent_v;
   a.dia = in_v;
   a.w_in = L.w_in;
@@ -479,10 +510,17 @@ static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shi
   a.xs = ep.xs;
   P3_TRY(prof_mark(A, PROF_BAND, 0, s));
   const unsigned grid = (unsigned)(8 * cdiv(L.ntiles, 8));
-  k_tile_product<V, X, K, EP, GEN><<<grid, TB, lds, s>>>(a);
+  k_tile_product<V, X, K, EP, GEN, E><<<grid, TB, lds, s>>>(a);
   P3_LAUNCHED();
   P3_TRY(prof_mark(A, PROF_BAND, 1, s));
   return PARS3_OK;
+}
+
+template <class V, class X, int K, bool EP, bool GEN>
+static pars3_status launch(pars3_matrix *A, const V *in_v, const V *ent_v, X shift, const X *x, X *y, hipStream_t s,
+                           const epilogue<X> &ep) {
+  if (A->lay.lgT <= ENT16_MAX_LGT) return launch_e<V, X, K, EP, GEN, uint16_t>(A, in_v, ent_v, shift, x, y, s, ep);
+  return launch_e<V, X, K, EP, GEN, uint32_t>(A, in_v, ent_v, shift, x, y, s, ep);
 }
 
 template <class V, class X>
@@ -602,7 +640,7 @@ pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, pr
   a->chunk_fix = L.chunk_fix.p;
   a->ovf_ptr = L.ovf_ptr.p;
   a->chunk_ovf = L.chunk_ovf.p;
-  a->ent_rc = L.ent_rc.p;
+  a->ent_rc = L.lgT <= ENT16_MAX_LGT ? (const void *)L.ent_rc16.p : (const void *)L.ent_rc.p;
   a->w_in = L.w_in;
   a->ntiles = L.ntiles;
   a->lgT = L.lgT;
@@ -632,49 +670,58 @@ pars3_status make_task(const pars3_matrix *A, int vec_dtype, int value_dtype, pr
   return PARS3_OK;
 }
 
-template <class V, class X, int K, bool EP, bool GEN>
-static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, const int32_t *qbeg, int32_t grid,
+template <class V, class X, int K, bool EP, bool GEN, int EW>
+static pars3_status launch_batch_e(const prod_task *tasks, const int2 *items, const int32_t *qbeg, int32_t grid,
                                    int32_t maxT, hipStream_t s) {
   const size_t lds = (size_t)maxT * KP<K> * sizeof(double);
   static bool raised = false;
   if (!raised && lds + sizeof(double) * (TB / 64) + 64 > LDS_DEFAULT) {
-    P3_TRY(raise_lds(k_batch_product<V, X, K, EP, GEN>, (size_t)1024 * KP<K> * sizeof(double)));
+    P3_TRY(raise_lds(k_batch_product<V, X, K, EP, GEN, EW>, (size_t)1024 * KP<K> * sizeof(double)));
     raised = true;
   }
-  k_batch_product<V, X, K, EP, GEN><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
+  k_batch_product<V, X, K, EP, GEN, EW><<<(unsigned)grid, TB, lds, s>>>(tasks, items, qbeg);
   P3_LAUNCHED();
   return PARS3_OK;
 }
 
+template <class V, class X, int K, bool EP, bool GEN>
+static pars3_status launch_batch_k(const prod_task *tasks, const int2 *items, const int32_t *qbeg, int32_t grid,
+                                   int32_t minT, int32_t maxT, hipStream_t s) {
+  constexpr int32_t T16 = 1 << ENT16_MAX_LGT;
+  if (maxT <= T16) return launch_batch_e<V, X, K, EP, GEN, 2>(tasks, items, qbeg, grid, maxT, s);
+  if (minT > T16) return launch_batch_e<V, X, K, EP, GEN, 4>(tasks, items, qbeg, grid, maxT, s);
+  return launch_batch_e<V, X, K, EP, GEN, 0>(tasks, items, qbeg, grid, maxT, s);
+}
+
 template <class V, class X, bool GEN>
 static pars3_status launch_batch_g(int k, const prod_task *tasks, const int2 *items, const int32_t *qbeg,
-                                   int32_t grid, int32_t maxT, hipStream_t s) {
+                                   int32_t grid, int32_t minT, int32_t maxT, hipStream_t s) {
   switch (k) {
-    case 1: return launch_batch_k<V, X, 1, false, GEN>(tasks, items, qbeg, grid, maxT, s);
-    case 2: return launch_batch_k<V, X, 2, false, GEN>(tasks, items, qbeg, grid, maxT, s);
-    case 4: return launch_batch_k<V, X, 4, false, GEN>(tasks, items, qbeg, grid, maxT, s);
-    case 8: return launch_batch_k<V, X, 8, false, GEN>(tasks, items, qbeg, grid, maxT, s);
+    case 1: return launch_batch_k<V, X, 1, false, GEN>(tasks, items, qbeg, grid, minT, maxT, s);
+    case 2: return launch_batch_k<V, X, 2, false, GEN>(tasks, items, qbeg, grid, minT, maxT, s);
+    case 4: return launch_batch_k<V, X, 4, false, GEN>(tasks, items, qbeg, grid, minT, maxT, s);
+    case 8: return launch_batch_k<V, X, 8, false, GEN>(tasks, items, qbeg, grid, minT, maxT, s);
     default: return fail(PARS3_EINVAL, "batch: k must be 1, 2, 4 or 8 (got %d)", k);
   }
 }
 
 template <class V, class X>
 static pars3_status launch_batch_v(int k, bool ep, bool gen, const prod_task *tasks, const int2 *items,
-                                   const int32_t *qbeg, int32_t grid, int32_t maxT, hipStream_t s) {
+                                   const int32_t *qbeg, int32_t grid, int32_t minT, int32_t maxT, hipStream_t s) {
   if (ep) {
     if (k != 1) return fail(PARS3_EINVAL, "batch: the solver epilogue takes one right-hand side");
     if (gen) return fail(PARS3_ESTATE, "batch: the solver epilogue needs skew matrices without diagonal");
-    return launch_batch_k<V, X, 1, true, false>(tasks, items, qbeg, grid, maxT, s);
+    return launch_batch_k<V, X, 1, true, false>(tasks, items, qbeg, grid, minT, maxT, s);
   }
-  if (gen) return launch_batch_g<V, X, true>(k, tasks, items, qbeg, grid, maxT, s);
-  return launch_batch_g<V, X, false>(k, tasks, items, qbeg, grid, maxT, s);
+  if (gen) return launch_batch_g<V, X, true>(k, tasks, items, qbeg, grid, minT, maxT, s);
+  return launch_batch_g<V, X, false>(k, tasks, items, qbeg, grid, minT, maxT, s);
 }
 
 pars3_status launch_batch(int vkind, int k, bool ep, bool gen, const prod_task *tasks, const int2 *items,
-                          const int32_t *qbeg, int32_t grid, int32_t maxT, hipStream_t s) {
-  if (vkind == PARS3_F64) return launch_batch_v<double, double>(k, ep, gen, tasks, items, qbeg, grid, maxT, s);
-  if (vkind == PARS3_F32) return launch_batch_v<float, float>(k, ep, gen, tasks, items, qbeg, grid, maxT, s);
-  return launch_batch_v<uint16_t, float>(k, ep, gen, tasks, items, qbeg, grid, maxT, s);
+                          const int32_t *qbeg, int32_t grid, int32_t minT, int32_t maxT, hipStream_t s) {
+  if (vkind == PARS3_F64) return launch_batch_v<double, double>(k, ep, gen, tasks, items, qbeg, grid, minT, maxT, s);
+  if (vkind == PARS3_F32) return launch_batch_v<float, float>(k, ep, gen, tasks, items, qbeg, grid, minT, maxT, s);
+  return launch_batch_v<uint16_t, float>(k, ep, gen, tasks, items, qbeg, grid, minT, maxT, s);
 }
 
 }  // namespace p3

@@ -17,8 +17,9 @@ def test_several_gpus_refused(capsys):
 
 
 def test_kernel_names():
-    assert bench.kernel_name("f64") == "p3::k_tile_product<double, double, 1, false, false>"
-    assert bench.kernel_name("bf16") == "p3::k_tile_product<unsigned short, float, 1, false, false>"
+    assert bench.kernel_name("f64") == "p3::k_tile_product<double, double, 1, false, false, unsigned short>"
+    assert bench.kernel_name("bf16") == "p3::k_tile_product<unsigned short, float, 1, false, false, unsigned short>"
+    assert bench.kernel_name("f32", 512) == "p3::k_tile_product<float, float, 1, false, false, unsigned int>"
 
 
 def test_algorithmic_bytes():
@@ -37,4 +38,7 @@ def test_traffic_only_for_matching_sources(monkeypatch):
         h = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("source_sha256:")][0]
     monkeypatch.setattr(bench, "source_hash", lambda: h)
     assert bench.measured_traffic("f64") > 1e8
+    # taken on 256-row tiles without an inner band: no figure for other layouts
+    assert bench.measured_traffic("f64", tile_rows=512) is None
+    assert bench.measured_traffic("f64", w_in=2) is None
     assert bench.measured_traffic("f32") is None or bench.measured_traffic("f32") > 0

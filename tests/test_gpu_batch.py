@@ -67,6 +67,47 @@ def test_batch_products_match_oracle(k, value_dtype):
         assert rel_inf(ys[i].cpu().numpy().astype(np.float64), want) <= tol, i
 
 
+@pytest.mark.parametrize("tiles", [128, 512])
+def test_batch_of_one_entry_width(tiles):
+    """Every matrix at one tile height: all 16-bit entry words (128 rows) or
+    all 32-bit ones (512 rows), each served by its own kernel (the mixed set
+    above takes the per-item choice)."""
+    specs, Ls = mixed_set(6, 41 + tiles)
+    print(f"[gpu] batch spmv one tile height T={tiles} sizes={[L.n for L in Ls]}", flush=True)
+    mats = reordered(Ls, p3.F32, tiles=tiles)
+    bat = p3.Batch(mats)
+    Xs = [synth.vector(L.n, 300 + i, 8) for i, L in enumerate(Ls)]
+    xs = [to_dev(X, torch.float32) for X in Xs]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    shifts = np.array([s["alpha"] for s in specs])
+    bat.spmv(xs, ys, shifts, k=8, vec_dtype=p3.F32)
+    torch.cuda.synchronize()
+    for i, L in enumerate(Ls):
+        want = oracle_product(L, shifts[i], Xs[i], p3.F32)
+        assert rel_inf(ys[i].cpu().numpy().astype(np.float64), want) <= 1e-5, i
+
+
+def test_batch_rejects_a_matrix_split_again():
+    """The work list and LDS size of a batch come from the layouts at its
+    creation; a matrix split again afterwards (here to taller tiles) is
+    refused before any launch."""
+    L = synth.grid2d(40, 3)
+    M = p3.Matrix(L).reorder(tile_rows=128)
+    bat = p3.Batch([M])
+    x = to_dev(synth.vector(L.n, 1))
+    y = torch.empty_like(x)
+    bat.spmv([x], [y], np.array([0.5]))
+    torch.cuda.synchronize()
+    M.reorder(tile_rows=512)
+    with pytest.raises(p3.Pars3Error) as e:
+        bat.spmv([x], [y], np.array([0.5]))
+    assert e.value.status == p3.ESTATE
+    b = to_dev(np.ones(L.n))
+    with pytest.raises(p3.Pars3Error) as e:
+        bat.mrs([1.0], [b], [torch.zeros_like(b)])
+    assert e.value.status == p3.ESTATE
+
+
 def test_batch_recapture_on_new_pointers_and_shifts():
     specs, Ls = mixed_set(6, 5)
     mats = reordered(Ls, p3.F64)
