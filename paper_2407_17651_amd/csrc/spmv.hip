@@ -236,14 +236,72 @@ __device__ __forceinline__ void group_add(const group_gathers<X, K> &h, double *
     }
 }
 
+// The x gathers and LDS adds of a group, for 8 right-hand sides: in H parts
+// of PRE / H chunks, since the x rows of all PRE chunks would hold 64
+// registers (128 for FP64) and leave room for 5 wavefronts per SIMD or fewer
+// instead of 8.  The group's entry loads still all go out together.
+template <class V, class X, int K, class E>
+__device__ __forceinline__ void gather_add_parts(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
+                                                 const group_entries<V> &g, gptr<X> x, double *ys) {
+  {
+    constexpr int H = sizeof(X) == 8 ? 4 : 2;
+    constexpr int QH = PRE / H;
+    int32_t slot[PRE], xrow[PRE];
+    X coef[PRE];
+#pragma unroll
+    for (int q = 0; q < PRE; q++) {
+      slot[q] = -1;
+      xrow[q] = 0;
+      coef[q] = (X)0;
+      if (d[q].y != CHUNK_EMPTY) {
+        const int32_t len = (int32_t)(d[q].y & 127u) + 1;
+        const bool col_side = (d[q].y >> 7) & 1u;
+        const int32_t other = (int32_t)(d[q].y >> 8);
+        int32_t ri, cj;
+        eword<E>::decode(g.rc[q], ri, cj);
+        const X val = vload<V>::template cvt<X>(g.vv[q]);
+        slot[q] = lane < len ? (col_side ? cj : ri) : -1;
+        xrow[q] = (other << lgT) + (col_side ? ri : cj);
+        coef[q] = col_side && !sym ? -val : val;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < H; h++) {
+      X xv[QH][K];
+#pragma unroll
+      for (int i = 0; i < QH; i++) {
+        const int q = h * QH + i;
+        if (d[q].y == CHUNK_EMPTY) {
+#pragma unroll
+          for (int c = 0; c < K; c++) xv[i][c] = (X)0;
+        } else {
+          rowvec<X, K>::load(x, xrow[q], xv[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < QH; i++) {
+        const int q = h * QH + i;
+        if (slot[q] >= 0) {
+#pragma unroll
+          for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * KP<K> + c], (double)(coef[q] * xv[i][c]));
+        }
+      }
+    }
+  }
+}
+
 template <class V, class X, int K, class E>
 __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
                                             gptr<E> ent_rc, gptr<V> ent_v, gptr<X> x, double *ys) {
   group_entries<V> g;
   group_load<V, E>(d, lane, ent_rc, ent_v, g);
-  group_gathers<X, K> h;
-  group_gather<V, X, K, E>(d, lane, lgT, sym, g, x, h);
-  group_add<X, K>(h, ys);
+  if constexpr (K < 8) {
+    group_gathers<X, K> h;
+    group_gather<V, X, K, E>(d, lane, lgT, sym, g, x, h);
+    group_add<X, K>(h, ys);
+  } else {
+    gather_add_parts<V, X, K, E>(d, lane, lgT, sym, g, x, ys);
+  }
 }
 
 // Output phase of a tile (after its LDS row sums are complete): y = (shift
@@ -392,10 +450,12 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   rowvec<X, K>::load(x, min((int64_t)r0 + threadIdx.x, (int64_t)n - 1), xown);
   for (int32_t s = threadIdx.x; s < rows * KP<K>; s += TB) ys[s] = 0.0;
   __syncthreads();
-  {
+  if constexpr (K < 8) {
     group_gathers<X, K> h;
     group_gather<V, X, K, E>(d, lane, lgT, GEN && a.sym != 0, g, x, h);
     group_add<X, K>(h, ys);
+  } else {
+    gather_add_parts<V, X, K, E>(d, lane, lgT, GEN && a.sym != 0, g, x, ys);
   }
   for (int32_t cb = o0 + wave; cb < o1; cb += (TB / 64) * PRE) {
 #pragma unroll
