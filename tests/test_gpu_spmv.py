@@ -56,9 +56,12 @@ def test_layout_variants(params):
 
 
 @pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32, p3.BF16])
-@pytest.mark.parametrize("params", [dict(), dict(w_in=3), dict(t_out=2), dict(tile_rows=64)])
+@pytest.mark.parametrize("params", [dict(), dict(w_in=3), dict(t_out=2), dict(tile_rows=64), dict(tile_rows=512),
+                                    dict(tile_rows=1024)])
 def test_integer_inputs_bit_exact(value_dtype, params):
-    """Values and x in {-4..4}: exact in every precision and summation order."""
+    """Values and x in {-4..4}: exact in every precision and summation order.
+    Tiles of up to 256 rows store 16-bit entry words, taller ones 32-bit
+    words; n = 8000 leaves a ragged last tile for every height."""
     L = synth.rgg2d(8000, 10.0, 12, "int4")
     print(f"[gpu] spmv integer dtype={value_dtype} {params}", flush=True)
     perm, B = oracle_reordered(L)
@@ -90,17 +93,22 @@ def test_block_right_hand_sides(k, value_dtype):
         assert rel_inf(got[:, c], one) <= TOL[value_dtype]
 
 
+@pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32])
 @pytest.mark.parametrize("tile_rows,k", [(1024, 8), (512, 8), (64, 8)])
-def test_block_right_hand_sides_tile_sizes(tile_rows, k):
+def test_block_right_hand_sides_tile_sizes(tile_rows, k, value_dtype):
     """Largest LDS accumulator (1024 rows x 8 right-hand sides in FP64) and
-    the smallest tiles."""
+    the smallest tiles, with 32-bit (1024, 512) and 16-bit (64) entry words;
+    8 right-hand sides take the gathers of a group in parts."""
     L = synth.rgg2d(30000, 12.0, 17)
-    print(f"[gpu] spmv tile_rows={tile_rows} k={k}", flush=True)
+    print(f"[gpu] spmv tile_rows={tile_rows} k={k} dtype={value_dtype}", flush=True)
     perm, B = oracle_reordered(L)
-    M = p3.Matrix(L).reorder(tile_rows=tile_rows)
+    M = p3.Matrix(L).reorder(tile_rows=tile_rows, value_dtype=value_dtype)
     X = synth.vector(L.n, 6, k)
-    got = gpu_spmv(M, -0.5, X, p3.F64)
-    assert rel_inf(got, oracle.spmv(B, -0.5, X)) <= 1e-12
+    vec = p3.F64 if value_dtype == p3.F64 else p3.F32
+    Xr = X if vec == p3.F64 else X.astype(np.float32).astype(np.float64)
+    Bv = type(B)(**{**B.__dict__, "val": oracle.rounded_values(B.val, "f64" if vec == p3.F64 else "f32")})
+    got = gpu_spmv(M, -0.5, X, vec)
+    assert rel_inf(got, oracle.spmv(Bv, -0.5, Xr)) <= TOL[value_dtype]
 
 
 def test_misaligned_block_vectors_rejected():
