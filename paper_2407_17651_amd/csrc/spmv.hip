@@ -90,9 +90,9 @@ struct vload {
 // Entry words (row offset in its tile) << SH | (column offset in its tile):
 // 16-bit words with SH = 8 for tiles of at most 256 rows, 32-bit words with
 // SH = 16 for taller ones.  Loads return the word zero-extended in a full
-// register (one load per register: the compiler keeps the same load and wait
-// order for both widths, so no barrier is needed here; one measured 11 more
-// registers and slower solver epilogues).
+// register, one load per register.  The compiler then keeps the same load
+// and wait order for both widths, so no asm barrier is needed before the
+// decode (one there cost 11 registers and slowed the solver epilogues).
 template <class E>
 struct eword {
   static constexpr int SH = sizeof(E) == 2 ? 8 : 16;
@@ -243,48 +243,46 @@ __device__ __forceinline__ void group_add(const group_gathers<X, K> &h, double *
 template <class V, class X, int K, class E>
 __device__ __forceinline__ void gather_add_parts(const uint2 (&d)[PRE], int32_t lane, int32_t lgT, bool sym,
                                                  const group_entries<V> &g, gptr<X> x, double *ys) {
-  {
-    constexpr int H = sizeof(X) == 8 ? 4 : 2;
-    constexpr int QH = PRE / H;
-    int32_t slot[PRE], xrow[PRE];
-    X coef[PRE];
+  constexpr int H = sizeof(X) == 8 ? 4 : 2;
+  constexpr int QH = PRE / H;
+  int32_t slot[PRE], xrow[PRE];
+  X coef[PRE];
 #pragma unroll
-    for (int q = 0; q < PRE; q++) {
-      slot[q] = -1;
-      xrow[q] = 0;
-      coef[q] = (X)0;
-      if (d[q].y != CHUNK_EMPTY) {
-        const int32_t len = (int32_t)(d[q].y & 127u) + 1;
-        const bool col_side = (d[q].y >> 7) & 1u;
-        const int32_t other = (int32_t)(d[q].y >> 8);
-        int32_t ri, cj;
-        eword<E>::decode(g.rc[q], ri, cj);
-        const X val = vload<V>::template cvt<X>(g.vv[q]);
-        slot[q] = lane < len ? (col_side ? cj : ri) : -1;
-        xrow[q] = (other << lgT) + (col_side ? ri : cj);
-        coef[q] = col_side && !sym ? -val : val;
+  for (int q = 0; q < PRE; q++) {
+    slot[q] = -1;
+    xrow[q] = 0;
+    coef[q] = (X)0;
+    if (d[q].y != CHUNK_EMPTY) {
+      const int32_t len = (int32_t)(d[q].y & 127u) + 1;
+      const bool col_side = (d[q].y >> 7) & 1u;
+      const int32_t other = (int32_t)(d[q].y >> 8);
+      int32_t ri, cj;
+      eword<E>::decode(g.rc[q], ri, cj);
+      const X val = vload<V>::template cvt<X>(g.vv[q]);
+      slot[q] = lane < len ? (col_side ? cj : ri) : -1;
+      xrow[q] = (other << lgT) + (col_side ? ri : cj);
+      coef[q] = col_side && !sym ? -val : val;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < H; h++) {
+    X xv[QH][K];
+#pragma unroll
+    for (int i = 0; i < QH; i++) {
+      const int q = h * QH + i;
+      if (d[q].y == CHUNK_EMPTY) {
+#pragma unroll
+        for (int c = 0; c < K; c++) xv[i][c] = (X)0;
+      } else {
+        rowvec<X, K>::load(x, xrow[q], xv[i]);
       }
     }
 #pragma unroll
-    for (int h = 0; h < H; h++) {
-      X xv[QH][K];
+    for (int i = 0; i < QH; i++) {
+      const int q = h * QH + i;
+      if (slot[q] >= 0) {
 #pragma unroll
-      for (int i = 0; i < QH; i++) {
-        const int q = h * QH + i;
-        if (d[q].y == CHUNK_EMPTY) {
-#pragma unroll
-          for (int c = 0; c < K; c++) xv[i][c] = (X)0;
-        } else {
-          rowvec<X, K>::load(x, xrow[q], xv[i]);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < QH; i++) {
-        const int q = h * QH + i;
-        if (slot[q] >= 0) {
-#pragma unroll
-          for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * KP<K> + c], (double)(coef[q] * xv[i][c]));
-        }
+        for (int c = 0; c < K; c++) atomicAdd(&ys[slot[q] * KP<K> + c], (double)(coef[q] * xv[i][c]));
       }
     }
   }
