@@ -294,6 +294,26 @@ def main(argv=None):
         "measured_hbm_gbs": round(traffic / (t_band * 1e-3) / 1e9, 2) if traffic else None,
     }
 
+    # the same products with x and y in the caller's (input) numbering: a
+    # gather of x into RCM order, the product, a scatter of y back; the
+    # solvers permute once per solve instead, so this cost is reported apart
+    def ostep(s):
+        c = s % copies
+        p3.pars3_spmv(mats[c].h, shift, xs[c], ys[c], 1, vec, p3.ORDER_ORIGINAL)
+
+    for s in range(args.warmup):
+        ostep(s)
+    torch.cuda.synchronize()
+    o0, o1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    o0.record()
+    for s in range(args.steps):
+        ostep(s)
+    o1.record()
+    torch.cuda.synchronize()
+    oms = o0.elapsed_time(o1) / args.steps
+    out["original_order"] = {"ms": round(oms, 5), "permute_ms": round(oms - ms, 5),
+                             "time_vs_rcm_order": round(oms / ms, 3)}
+
     # full-CSR GPU products of the same matrix (both triangles stored), same
     # rotation; own CSR-vector kernel and rocSPARSE, RCM and input numbering
     if args.dtype in ("f64", "f32") and not args.no_csr:
