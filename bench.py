@@ -82,10 +82,10 @@ def skew_bytes(n, nnz, dtype, k=1):
 def batched(args, p3, synth, torch, np):
     """256 skew matrices (2D/3D stencils and random geometric graphs, n
     log-uniform in [2k, 200k]) with k = 8 FP32 right-hand sides in one
-    persistent graph-captured launch; then 256 MRS solves (alpha_i in
-    [0.1, 2], b_i = A_i 1) to 1e-10 together.  The tile height of the batch
-    is tuned per operation by timing whole batch launches (each matrix keeps
-    its reordering; only the split is rebuilt)."""
+    graph-captured launch (one workgroup per matrix tile); then 256 MRS
+    solves (alpha_i in [0.1, 2], b_i = A_i 1) to 1e-10 together.  The tile
+    height of the batch is tuned per operation by timing whole batch launches
+    (each matrix keeps its reordering; only the split is rebuilt)."""
     specs = synth.batch_specs(256)
     print("[bench] batched: generating 256 matrices", file=sys.stderr, flush=True)
     Ls = [synth.make(s, "uniform_f32") for s in specs]

@@ -1,5 +1,6 @@
-"""Batched products (one persistent graph-captured launch over many matrices,
-block right-hand sides) and batched MRS, against the oracle per matrix.
+"""Batched products (one graph-captured launch over many matrices, one
+workgroup per matrix tile, block right-hand sides) and batched MRS, against
+the oracle per matrix.
 
 Bars: as for single products (FP64 <= 1e-12, FP32 <= 1e-5 relative
 infinity-norm against the oracle on the same rounded values and vectors);
