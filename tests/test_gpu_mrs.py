@@ -93,6 +93,32 @@ def test_mixed_precision_reaches_fp64_residual(precision, inner_tol):
     assert err <= 1e-7
 
 
+@pytest.mark.parametrize("precision", [p3.F64, p3.F32])
+def test_repeated_solves_and_new_splits(precision):
+    """Solves in a row on one handle, and after new splits of its matrix
+    (other tile heights, 16- or 32-bit entry words), reuse the handle's
+    solver workspace.  Every solve meets the FP64 residual bound, and solves
+    of one split agree with each other."""
+    L = synth.grid3d(24, 7, "normal")
+    alpha = 0.5
+    b = oracle.spmv(L, alpha, np.ones(L.n))
+    keep = int(precision != p3.F64)
+    M = p3.Matrix(L).reorder(value_dtype=precision, keep_fp64=keep)
+    print(f"[gpu] mrs repeated solves precision={precision}", flush=True)
+    prev = None
+    # (tile height, split again before the solve); the handle starts at 256
+    for tiles, resplit in ((256, False), (256, False), (512, True), (512, False), (128, True), (256, True)):
+        if resplit:
+            M.reorder(value_dtype=precision, keep_fp64=keep, tile_rows=tiles)
+        st, info, _, x = solve(M, alpha, b, tol=1e-10, maxit=5000, precision=precision)
+        assert st == p3.OK, info
+        assert oracle.residual(L, alpha, b, x) <= 1e-10
+        if prev is not None and prev[0] == tiles:
+            assert abs(info["iters"] - prev[1]["iters"]) <= 1
+            assert rel_inf(x, prev[2]) <= 1e-9
+        prev = (tiles, info, x)
+
+
 def test_workload1_fp64_and_mixed():
     """3D 128^3 stencil with N(0,1) values, alpha = 0.5, b = A 1, to 1e-10."""
     L = synth.workload(1)
