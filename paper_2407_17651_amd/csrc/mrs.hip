@@ -222,9 +222,16 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
     hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (ie != hipSuccess) st = fail(PARS3_EHIP, "mrs: graph instantiation failed: %s", hipGetErrorString(ie));
   }
+  // Replays between stop checks: at most check_every / 6, and once |eta| has
+  // been seen to fall, about as many as its observed rate per iteration says
+  // are still needed (iterations launched past the stop return at once but
+  // still cost two launches each).
   int32_t done = h.done;
-  const int32_t chunk = std::max(1, check_every / 6);
-  for (int32_t it = 0; st == PARS3_OK && !done && it < maxit; it += 6 * chunk) {
+  const int32_t chunk_max = std::max(1, check_every / 6);
+  int32_t chunk = chunk_max;
+  double eta_prev = std::fabs(beta1);
+  int32_t iter_prev = 0;
+  for (int32_t it = 0; st == PARS3_OK && !done && it < maxit;) {
     for (int32_t c = 0; c < chunk; c++) {
       hipError_t le = hipGraphLaunch(exec, s);
       if (le != hipSuccess) {
@@ -233,10 +240,24 @@ static pars3_status mrs_iterate(pars3_matrix *A, int value_dtype, double alpha, 
       }
     }
     if (st != PARS3_OK) break;
+    it += 6 * chunk;
     hipError_t me = hipMemcpyAsync(&h, dv, sizeof(h), hipMemcpyDeviceToHost, s);
     if (me == hipSuccess) me = hipStreamSynchronize(s);
     if (me != hipSuccess) st = fail(PARS3_EHIP, "mrs: %s", hipGetErrorString(me));
     done = h.done;
+    const double eta_now = std::fabs(h.eta[h.iter & 1]);
+    const int32_t di = h.iter - iter_prev;
+    chunk = chunk_max;
+    if (!done && di > 0 && eta_now > tol_abs && eta_now < eta_prev) {
+      const double per_iter = std::log(eta_now / eta_prev) / di;  // < 0
+      const double need = std::log(tol_abs / eta_now) / per_iter;  // iterations still needed, > 0
+      // with a margin of 10% and one replay: a check that finds the solve
+      // still running costs a host round trip, about as much as several
+      // iterations past the stop
+      chunk = (int32_t)std::min<double>(chunk_max, std::max(1.0, std::ceil((1.1 * need + 6.0) / 6.0)));
+    }
+    eta_prev = eta_now;
+    iter_prev = h.iter;
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
