@@ -293,9 +293,12 @@ pars3_status pars3_features(const pars3_matrix *A, double *f);
  * for shifted skew-symmetric systems that motivates the product; each
  * iteration costs one product with S and one inner product).  x_k minimises
  * ||b - A x|| over x_0 + K_k(S, r_0) by a skew Lanczos recurrence with Givens
- * rotations.  Every iteration runs on the device (product with a fused
- * epilogue, one scalar kernel, one vector kernel, replayed from a hipGraph);
- * the host polls the stop flag every check_every iterations.
+ * rotations.  Every iteration runs on the device (the product with a fused
+ * epilogue that also applies the previous iteration's vector update, and one
+ * scalar kernel, replayed from a hipGraph);
+ * the host polls the stop flag at most every check_every iterations (rounded
+ * down to whole six-iteration replays, at least one), sooner when the
+ * observed rate of |eta| says the tolerance is near.
  *
  * precision = PARS3_F64: the whole iteration in FP64 (needs FP64 values).
  * precision = PARS3_F32 / PARS3_BF16: mixed precision; FP64 iterative
@@ -322,7 +325,7 @@ pars3_status pars3_features(const pars3_matrix *A, double *f);
 typedef struct {
   double tol;           /* relative residual target (default 1e-10) */
   int32_t maxit;        /* iteration limit (default 10000) */
-  int32_t check_every;  /* iterations between host polls of the stop flag (default 32) */
+  int32_t check_every;  /* most iterations between host polls of the stop flag (default 32) */
   int32_t precision;    /* PARS3_F64 (default), PARS3_F32 or PARS3_BF16 */
   double inner_tol;     /* mixed: relative reduction of each inner solve (0 = default) */
   int32_t max_refine;   /* mixed: maximum number of refinements (default 30) */
