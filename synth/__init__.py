@@ -66,7 +66,10 @@ def _L():
         lib.syn_values.argtypes = [i64, u64, i, ctypes.c_void_p]
         lib.syn_rgg2d_radius.argtypes = [i64, d]
         lib.syn_rgg2d_radius.restype = d
-        for f in ("syn_grid2d", "syn_grid3d", "syn_rgg2d", "syn_chung_lu", "syn_from_edges"):
+        lib.syn_rgg3d.argtypes = [i64, d, u64, i, i, P]
+        lib.syn_rgg3d_radius.argtypes = [i64, d]
+        lib.syn_rgg3d_radius.restype = d
+        for f in ("syn_grid2d", "syn_grid3d", "syn_rgg2d", "syn_rgg3d", "syn_chung_lu", "syn_from_edges"):
             getattr(lib, f).restype = i
         _lib = lib
     return _lib
@@ -121,6 +124,17 @@ def rgg2d(n: int, deg: float, seed: int, values: str = "uniform", relabel: bool 
 
 def rgg2d_radius(n: int, deg: float) -> float:
     return float(_L().syn_rgg2d_radius(n, deg))
+
+
+def rgg3d(n: int, deg: float, seed: int, values: str = "uniform", relabel: bool = True) -> Lower:
+    """Random geometric graph in the unit cube with expected mean degree deg."""
+    sm = _SynMatrix()
+    _check(_L().syn_rgg3d(n, deg, seed, VALUES[values], int(relabel), ctypes.byref(sm)), "rgg3d")
+    return _take(sm, f"rgg3d_{n}")
+
+
+def rgg3d_radius(n: int, deg: float) -> float:
+    return float(_L().syn_rgg3d_radius(n, deg))
 
 
 def chung_lu(n: int, deg: float, gamma: float, seed: int, values: str = "uniform", relabel: bool = True) -> Lower:

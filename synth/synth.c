@@ -296,6 +296,112 @@ oom:
   return SYN_ENOMEM;
 }
 
+/* Radius r such that (n-1) * P(|X - Y| < r) = deg for X, Y uniform in the unit
+ * cube, with P = 4 pi r^3 / 3 - 3 pi r^4 / 2 + 8 r^5 / 5 - r^6 / 6 (the
+ * distribution function of the distance between two uniform points of the
+ * unit cube, valid for r <= 1). */
+double syn_rgg3d_radius(int64_t n, double deg) {
+  if (n < 2) return 0.0;
+  const double pi = 3.141592653589793;
+  double lo = 0.0, hi = 1.0, target = deg / (double)(n - 1);
+  for (int it = 0; it < 200; it++) {
+    double r = 0.5 * (lo + hi);
+    double r3 = r * r * r;
+    double p = 4.0 * pi * r3 / 3.0 - 1.5 * pi * r3 * r + 1.6 * r3 * r * r - r3 * r3 / 6.0;
+    if (p < target) lo = r; else hi = r;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* Random geometric graph in 3D: n points uniform in [0,1)^3, an edge when the
+ * Euclidean distance is strictly below r; cell-grid binning with cells no
+ * smaller than r, each unordered pair examined once (own cell, then the 13
+ * neighbouring cells that come later in (z, y, x) order). */
+int syn_rgg3d(int64_t n, double deg, uint64_t seed, int value_kind, int relabel, syn_matrix *out) {
+  if (n < 0 || n > 0x7fffffffLL) return SYN_EINVAL;
+  double r = syn_rgg3d_radius(n, deg);
+  double r2 = r * r;
+  double *px = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double *py = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double *pz = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  uint64_t ss = stream_seed(seed, 0);
+  int64_t nc = (r > 0.0) ? (int64_t)floor(1.0 / r) : 1;
+  if (nc > (int64_t)cbrt((double)n) + 1) nc = (int64_t)cbrt((double)n) + 1;  /* about one cell per point at most */
+  if (nc < 1) nc = 1;
+  int64_t ncell = nc * nc * nc;
+  int64_t *cstart = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+  int32_t *pts = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int64_t *cell = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  edge_list e = {0};
+  if (!px || !py || !pz || !cstart || !pts || !cell) goto oom;
+  for (int64_t i = 0; i < n; i++) {
+    px[i] = sm_u01(&ss);
+    py[i] = sm_u01(&ss);
+    pz[i] = sm_u01(&ss);
+    int64_t cx = (int64_t)(px[i] * (double)nc), cy = (int64_t)(py[i] * (double)nc),
+            cz = (int64_t)(pz[i] * (double)nc);
+    if (cx >= nc) cx = nc - 1;
+    if (cy >= nc) cy = nc - 1;
+    if (cz >= nc) cz = nc - 1;
+    cell[i] = (cz * nc + cy) * nc + cx;
+    cstart[cell[i] + 1]++;
+  }
+  for (int64_t q = 0; q < ncell; q++) cstart[q + 1] += cstart[q];
+  {
+    int64_t *fill = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+    if (!fill) goto oom;
+    memcpy(fill, cstart, (size_t)ncell * sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) pts[fill[cell[i]]++] = (int32_t)i;
+    free(fill);
+  }
+  {
+    /* the 13 of the 26 neighbouring cells that follow the own cell */
+    int off[13][3], no = 0;
+    for (int dz = -1; dz <= 1; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++)
+          if (dz > 0 || (dz == 0 && dy > 0) || (dz == 0 && dy == 0 && dx > 0)) {
+            off[no][0] = dx;
+            off[no][1] = dy;
+            off[no][2] = dz;
+            no++;
+          }
+    for (int64_t cz = 0; cz < nc; cz++)
+      for (int64_t cy = 0; cy < nc; cy++)
+        for (int64_t cx = 0; cx < nc; cx++) {
+          int64_t q = (cz * nc + cy) * nc + cx;
+          for (int64_t s = cstart[q]; s < cstart[q + 1]; s++) {
+            int32_t i = pts[s];
+            for (int64_t t = s + 1; t < cstart[q + 1]; t++) {
+              int32_t j = pts[t];
+              double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
+              if (dx * dx + dy * dy + dz * dz < r2 && el_push(&e, i, j)) goto oom;
+            }
+            for (int d = 0; d < no; d++) {
+              int64_t ox = cx + off[d][0], oy = cy + off[d][1], oz = cz + off[d][2];
+              if (ox < 0 || ox >= nc || oy < 0 || oy >= nc || oz < 0 || oz >= nc) continue;
+              int64_t o = (oz * nc + oy) * nc + ox;
+              for (int64_t t = cstart[o]; t < cstart[o + 1]; t++) {
+                int32_t j = pts[t];
+                double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
+                if (dx * dx + dy * dy + dz * dz < r2 && el_push(&e, i, j)) goto oom;
+              }
+            }
+          }
+        }
+  }
+  free(px); free(py); free(pz); free(cstart); free(pts); free(cell);
+  {
+    int rc = finish(n, &e, seed, value_kind, relabel, out);
+    el_free(&e);
+    return rc;
+  }
+oom:
+  free(px); free(py); free(pz); free(cstart); free(pts); free(cell);
+  el_free(&e);
+  return SYN_ENOMEM;
+}
+
 /* Chung-Lu graph with expected degrees w_i = C (i + i0)^(-1/(gamma-1)),
  * i = 0..n-1 (non-increasing).  C makes the mean weight equal `deg`; i0 is
  * chosen so that w_0^2 = sum(w), which keeps every pair probability

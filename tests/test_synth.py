@@ -43,6 +43,61 @@ def test_rgg_brute_force_small():
     assert len(set(zip(rows.tolist(), m.col.tolist()))) == m.nnz
 
 
+def _splitmix_u01(seed, k, count):
+    """count uniforms of stream k of a seed: SplitMix64 (Steele, Lea and
+    Flood), the stream's state being one output of the generator started at
+    seed ^ (0xD1B54A32D192ED03 (k + 1)), top 53 bits scaled to [0, 1)."""
+    mask = (1 << 64) - 1
+
+    def step(state):
+        state = (state + 0x9E3779B97F4A7C15) & mask
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        return state, z ^ (z >> 31)
+
+    _, state = step((seed ^ ((0xD1B54A32D192ED03 * (k + 1)) & mask)) & mask)
+    out = np.empty(count)
+    for q in range(count):
+        state, z = step(state)
+        out[q] = (z >> 11) * 2.0 ** -53
+    return out
+
+
+def test_rgg3d_degree_law():
+    """The radius solves (n - 1) P(|X - Y| < r) = deg with the distance law of
+    two uniform points in the unit cube; the realised mean degree follows."""
+    for n, deg in ((20_000, 30.0), (50_000, 43.7)):
+        m = synth.rgg3d(n, deg, 3)
+        assert abs(2 * m.nnz / m.n - deg) < 0.01 * deg
+    # small radii: P ~ 4 pi r^3 / 3 - 3 pi r^4 / 2 (ball volume less the
+    # first boundary correction; the next term is O(r^2) relative)
+    r = synth.rgg3d_radius(10**9, 10.0)
+    p2 = 4.0 * np.pi * r**3 / 3.0 - 1.5 * np.pi * r**4
+    assert abs(p2 * (10**9 - 1) / 10.0 - 1.0) < 1e-5
+
+
+def test_rgg3d_brute_force_small():
+    """Unrelabelled 3D RGG edges equal the brute-force set of pairs closer
+    than r, on points regenerated from the generator's own stream."""
+    n, deg, seed = 400, 12.0, 5
+    m = synth.rgg3d(n, deg, seed, relabel=False)
+    r = synth.rgg3d_radius(n, deg)
+    pts = _splitmix_u01(seed, 0, 3 * n).reshape(n, 3)
+    rows = np.repeat(np.arange(m.n), np.diff(m.rowptr))
+    got = set(zip(rows.tolist(), m.col.tolist()))
+    want, near = set(), set()
+    for i in range(n):
+        d = pts[:i] - pts[i]
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        for j in np.nonzero(d2 < r * r)[0]:
+            want.add((i, int(j)))
+        for j in np.nonzero(np.abs(d2 - r * r) < 1e-12)[0]:
+            near.add((i, int(j)))
+    assert len(want) > n  # the test covers a connected-ish graph
+    assert got - near == want - near
+
+
 def test_chung_lu_mean_degree():
     m = synth.chung_lu(50_000, 16.0, 2.5, 9)
     assert 14.0 < 2 * m.nnz / m.n < 17.0
