@@ -211,6 +211,52 @@ def table1(args, p3, synth, torch):
                         "paper's Table 1 matrices, U[-1,1] values, random relabelling", "matrices": rows}
 
 
+def workload2(args, p3, synth, torch):
+    """The 4M-row random geometric graph (mean degree 16): skew product
+    against rocSPARSE on the full CSR of the same reordered matrix, FP64 and
+    FP32, rotating over enough copies to exceed the Infinity Cache."""
+    dev = torch.device("cuda:0")
+    print("[bench] workload 2: RGG n = 4M, mean degree 16", file=sys.stderr, flush=True)
+    L = synth.workload(2)
+    n, nnz = L.n, L.nnz
+    res = {"workload": "random geometric graph in the unit square, n = 4,000,000, mean degree 16, U[-1,1] values, "
+                       "random relabelling, RCM + paper split", "n": n, "nnz_lower": nnz}
+    for dt, vdt, vec, tdt in (("f64", p3.F64, p3.F64, torch.float64), ("f32", p3.F32, p3.F32, torch.float32)):
+        B = skew_bytes(n, nnz, dt)
+        copies = max(2, math.ceil(768e6 / B))
+        mats = [p3.Matrix(L).reorder(value_dtype=vdt) for _ in range(copies)]
+        info = mats[0].info()
+        x0 = torch.from_numpy(synth.vector(n, 1501)).to(dev, tdt)
+        xs = [x0.clone() for _ in range(copies)]
+        ys = [torch.empty_like(x0) for _ in range(copies)]
+        cs = [p3.pars3_csr_create(m.h, p3.ORDER_RCM, vdt) for m in mats]
+
+        def timed(fn):
+            for s in range(args.warmup):
+                fn(s)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for s in range(args.steps):
+                fn(s)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / args.steps
+
+        ms = timed(lambda s: p3.pars3_spmv(mats[s % copies].h, 0.0, xs[s % copies], ys[s % copies], 1, vec,
+                                           p3.ORDER_RCM))
+        cms = timed(lambda s: p3.pars3_csr_spmv(cs[s % copies], 0.0, xs[s % copies], ys[s % copies], 1))
+        res[dt] = {"beta": info["beta"], "tile_rows": info["tile_rows"], "skew_ms": round(ms, 5),
+                   "skew_gbs": round(B / (ms * 1e-3) / 1e9, 1), "rocsparse_full_csr_ms": round(cms, 5),
+                   "skew_speedup": round(cms / ms, 3)}
+        for c in cs:
+            p3.pars3_csr_destroy(c)
+        del mats, cs, xs, ys
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +274,8 @@ def main(argv=None):
     ap.add_argument("--w-in", type=int, default=-1, help="inner band half-width (-1 = the paper split, 0)")
     ap.add_argument("--mrs-reps", type=int, default=3, help="timed solves per MRS precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix workload")
+    ap.add_argument("--workload2", action="store_true",
+                    help="also time the 4M-row random geometric graph (FP64 and FP32, against rocSPARSE)")
     ap.add_argument("--table1", action="store_true",
                     help="also time the stand-ins for the paper's six test matrices (about a minute)")
     ap.add_argument("--warm-cache", action="store_true",
@@ -499,6 +547,9 @@ def main(argv=None):
 
     if not args.no_batch:
         out["batched"] = batched(args, p3, synth, torch, np)
+
+    if args.workload2:
+        out["workload2"] = workload2(args, p3, synth, torch)
 
     if args.table1:
         out["table1_standins"] = table1(args, p3, synth, torch)
