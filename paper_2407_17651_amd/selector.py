@@ -19,7 +19,7 @@ boundary t_out, tile height) and is learned:
   tiles) and the single configuration best on average over the training set.
 
 Command line (GPU):
-  python -m paper_2407_17651_amd.selector sweep --start 0 --count 500 --out gpurun_out/sweep_0.npz
+  python -m paper_2407_17651_amd.selector sweep --start 0 --count 500 --out sweep_0.npz
   python -m paper_2407_17651_amd.selector merge OUT IN [IN ...]
   python -m paper_2407_17651_amd.selector evaluate [--data FILE]
 """
