@@ -361,9 +361,11 @@ pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const double *b, dou
  * one workgroup per item, the workgroups of an XCD taking its queue in order;
  * each launch is captured in a hipGraph and replayed.
  *  pars3_batch_create: m reordered handles (the batch keeps pointers to them;
- *    they must outlive it).  A handle split again (pars3_reorder) after the
- *    batch was made changes its tiles: pars3_batch_spmv and
- *    pars3_batch_mrs_solve then return ESTATE before any launch.
+ *    they must outlive it).  The work list is fixed from the handles' tiles
+ *    at creation: if a handle is split again (pars3_reorder) with another
+ *    tile height or tile count, pars3_batch_spmv and pars3_batch_mrs_solve
+ *    return ESTATE before any launch; a new split with the same tiles is
+ *    used as it is.
  *  pars3_batch_info: number of items, grid size (8 times the longest queue)
  *    and the 9 queue boundaries (host outputs, each may be NULL).
  *  pars3_batch_spmv: y_i = shifts[i] x_i + D_i x_i + S_i x_i for every matrix
