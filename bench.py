@@ -74,6 +74,25 @@ def measured_traffic(dtype, tile_rows=256, w_in=0):
         return None
 
 
+def timed_steps(fn, copies, warmup, steps, torch):
+    """Average milliseconds per call of fn(s) over `steps` timed calls.  Every
+    rotation copy is used once first (its first use may run one-time work
+    such as a library's analysis), then `warmup` untimed calls, then the
+    timed ones between two HIP events on the current stream."""
+    for c in range(copies):
+        fn(c)
+    for s in range(warmup):
+        fn(s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for s in range(steps):
+        fn(s)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def skew_bytes(n, nnz, dtype, k=1):
     sv, sx = SIZES[dtype]
     return nnz * (sv + 4) + (n + 1) * 4 + n * k * (sx + sx)
@@ -184,16 +203,7 @@ def table1(args, p3, synth, torch):
         cs = [p3.pars3_csr_create(m.h, p3.ORDER_RCM, p3.F64) for m in mats]
 
         def timed(fn):
-            for s in range(args.warmup):
-                fn(s)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for s in range(args.steps):
-                fn(s)
-            e1.record()
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / args.steps
+            return timed_steps(fn, copies, args.warmup, args.steps, torch)
 
         ms = timed(lambda s: p3.pars3_spmv(mats[s % copies].h, 0.0, xs[s % copies], ys[s % copies], 1, p3.F64,
                                            p3.ORDER_RCM))
@@ -232,16 +242,7 @@ def workload2(args, p3, synth, torch):
         cs = [p3.pars3_csr_create(m.h, p3.ORDER_RCM, vdt) for m in mats]
 
         def timed(fn):
-            for s in range(args.warmup):
-                fn(s)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for s in range(args.steps):
-                fn(s)
-            e1.record()
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / args.steps
+            return timed_steps(fn, copies, args.warmup, args.steps, torch)
 
         ms = timed(lambda s: p3.pars3_spmv(mats[s % copies].h, 0.0, xs[s % copies], ys[s % copies], 1, vec,
                                            p3.ORDER_RCM))
@@ -257,6 +258,71 @@ def workload2(args, p3, synth, torch):
     return res
 
 
+def host_cores():
+    """Cores this process may run on (the container's share of the host)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover - not Linux
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(args, oracle, synth, np, L, shift, mrs_out):
+    """The oracle timed on the host's cores, on bounded samples of the same
+    workload: its full-CSR FP64 product on one core (the reported value) and
+    on every core (rows shared among threads, the same sums), the paper's
+    serial SSS skew product on one core, and its FP64 MRS on one core to the
+    FP64 residual 1e-10 on the small 2D workload and on this one."""
+    n, nnz = L.n, L.nnz
+    Bm = oracle.permute(L, oracle.rcm(L))  # the oracle's own reordering
+    frow, fcol, fval = oracle.full_csr(Bm, shift)
+    xh = synth.vector(n, 1101)
+    budget = args.cpu_seconds
+
+    def sample(fn, seconds):
+        reps, t = 0, 0.0
+        while t < seconds and reps < 10000:
+            t1 = time.perf_counter()
+            fn()
+            t += time.perf_counter() - t1
+            reps += 1
+        return t / reps * 1e3, reps
+
+    cpu_ms, reps = sample(lambda: oracle.csr_spmv(frow, fcol, fval, xh), budget / 2)
+    par_ms, preps = sample(lambda: oracle.csr_spmv_par(frow, fcol, fval, xh), max(1.0, budget / 8))
+    sss_ms, sreps = sample(lambda: oracle.sss_spmv(Bm, shift, xh), max(1.0, budget / 8))
+    Bf = skew_bytes(n, nnz, "f64")
+    res = {
+        "value": round(Bf / (cpu_ms * 1e-3) / 1e9, 3),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "ms_per_product": round(cpu_ms, 3),
+        "sample": f"{reps} oracle full-CSR FP64 products (plain C, one thread) of the same reordered "
+                  f"3D 128^3 matrix; throughput counted with the FP64 skew byte count",
+        "host_cores": host_cores(),
+        "all_cores": {"cores": oracle.num_threads(), "ms_per_product": round(par_ms, 3),
+                      "gbs": round(Bf / (par_ms * 1e-3) / 1e9, 3),
+                      "sample": f"{preps} oracle full-CSR FP64 products with the rows shared among "
+                                f"{oracle.num_threads()} OpenMP threads"},
+        "sss_ms_per_product": round(sss_ms, 3),
+        "sss_sample": f"{sreps} oracle serial SSS skew products (one thread)",
+    }
+    if mrs_out is not None:
+        # oracle FP64 MRS to the FP64 relative residual 1e-10, one thread,
+        # in full: the small 2D workload (alpha = 1) and this one (alpha = 0.5)
+        mrs = {}
+        for name, Lm, alpha in (("workload0_2d_100x100", synth.workload(0), 1.0),
+                                ("workload1_3d_128", L, 0.5)):
+            bh = oracle.spmv(Lm, alpha, np.ones(Lm.n))
+            t1 = time.perf_counter()
+            _, info, _ = oracle.mrs(Lm, alpha, bh, tol=1e-10, maxit=20000)
+            ms = (time.perf_counter() - t1) * 1e3
+            mrs[name] = {"ms": round(ms, 1), "iters": info["iters"], "relres": info["relres"],
+                         "ms_per_iter": round(ms / max(info["iters"], 1), 3)}
+        res["mrs_fp64_one_core"] = mrs
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,7 +330,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--dtype", choices=sorted(SIZES), default="f64")
     ap.add_argument("--copies", type=int, default=0, help="rotation copies (0 = enough for 768 MB)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="budget of the oracle product samples")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-csr", action="store_true", help="skip the full-CSR comparison")
     ap.add_argument("--no-mrs", action="store_true", help="skip the MRS time-to-solution runs")
@@ -333,16 +399,7 @@ def main(argv=None):
         c = s % copies
         p3.pars3_spmv(mats[c].h, shift, xs[c], ys[c], 1, vec, p3.ORDER_RCM)
 
-    for s in range(args.warmup):
-        step(s)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for s in range(args.steps):
-        step(s)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = timed_steps(step, copies, args.warmup, args.steps, torch)
     value = B / (ms * 1e-3) / 1e9
 
     # same products without rotation (Infinity-Cache resident), for context
@@ -408,16 +465,7 @@ def main(argv=None):
         c = s % copies
         p3.pars3_spmv(mats[c].h, shift, xs[c], ys[c], 1, vec, p3.ORDER_ORIGINAL)
 
-    for s in range(args.warmup):
-        ostep(s)
-    torch.cuda.synchronize()
-    o0, o1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    o0.record()
-    for s in range(args.steps):
-        ostep(s)
-    o1.record()
-    torch.cuda.synchronize()
-    oms = o0.elapsed_time(o1) / args.steps
+    oms = timed_steps(ostep, copies, args.warmup, args.steps, torch)
     out["original_order"] = {"ms": round(oms, 5), "permute_ms": round(oms - ms, 5),
                              "time_vs_rcm_order": round(oms / ms, 3)}
 
@@ -432,16 +480,7 @@ def main(argv=None):
                 def cstep(s, cs=cs, eng=eng):
                     c = s % copies
                     p3.pars3_csr_spmv(cs[c], 0.0, xs[c], ys[c], eng)
-                for s in range(args.warmup):
-                    cstep(s)
-                torch.cuda.synchronize()
-                c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                c0.record()
-                for s in range(args.steps):
-                    cstep(s)
-                c1.record()
-                torch.cuda.synchronize()
-                cms = c0.elapsed_time(c1) / args.steps
+                cms = timed_steps(cstep, copies, args.warmup, args.steps, torch)
                 csr[f"{ename}_{oname}"] = {"ms": round(cms, 5), "gbs_csr_bytes": round(Bc / (cms * 1e-3) / 1e9, 1)}
             for c in cs:
                 p3.pars3_csr_destroy(c)
@@ -459,16 +498,7 @@ def main(argv=None):
             c = s % copies
             p3.pars3_spmv(smats[c].h, shift, xs[c], ys[c], 1, vec, p3.ORDER_RCM)
 
-        for s in range(args.warmup):
-            sstep(s)
-        torch.cuda.synchronize()
-        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s0.record()
-        for s in range(args.steps):
-            sstep(s)
-        s1.record()
-        torch.cuda.synchronize()
-        sms = s0.elapsed_time(s1) / args.steps
+        sms = timed_steps(sstep, copies, args.warmup, args.steps, torch)
         Bs = B + n * SIZES[args.dtype][1]
         out["symmetric_diag"] = {"ms": round(sms, 5), "gbs": round(Bs / (sms * 1e-3) / 1e9, 2),
                                  "algorithmic_bytes": Bs, "time_vs_skew": round(sms / ms, 3)}
@@ -557,47 +587,7 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline leg only
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        Bm = oracle.permute(L, oracle.rcm(L))  # the oracle's own reordering
-        frow, fcol, fval = oracle.full_csr(Bm, shift)
-        xh = synth.vector(n, 1101)
-        reps, t_cpu = 0, 0.0
-        while t_cpu < args.cpu_seconds and reps < 10000:
-            t1 = time.perf_counter()
-            oracle.csr_spmv(frow, fcol, fval, xh)
-            t_cpu += time.perf_counter() - t1
-            reps += 1
-        cpu_ms = t_cpu / reps * 1e3
-        out["cpu_baseline"] = {
-            "value": round(skew_bytes(n, nnz, "f64") / (cpu_ms * 1e-3) / 1e9, 3),
-            "unit": "GB/s",
-            "cores": 1,
-            "kind": "oracle",
-            "ms_per_product": round(cpu_ms, 3),
-            "sample": f"{reps} oracle full-CSR FP64 products (plain C, one thread) of the same reordered "
-                      f"3D 128^3 matrix; throughput counted with the FP64 skew byte count",
-        }
-        # the paper's serial baseline: the skew product from the stored
-        # triangle (SSS), one thread, bounded sample
-        reps2, t2 = 0, 0.0
-        while t2 < max(1.0, args.cpu_seconds / 4) and reps2 < 10000:
-            t1 = time.perf_counter()
-            oracle.sss_spmv(Bm, shift, xh)
-            t2 += time.perf_counter() - t1
-            reps2 += 1
-        out["cpu_baseline"]["sss_ms_per_product"] = round(t2 / reps2 * 1e3, 3)
-        out["cpu_baseline"]["sss_sample"] = f"{reps2} oracle serial SSS skew products (one thread)"
-        if mrs_out is not None:
-            # oracle FP64 MRS: a bounded number of iterations, scaled to the
-            # GPU FP64 solve's iteration count
-            bh = oracle.spmv(L, 0.5, np.ones(n))
-            k = 10
-            t1 = time.perf_counter()
-            oracle.mrs(L, 0.5, bh, tol=0.0, maxit=k)
-            per_it = (time.perf_counter() - t1) / k * 1e3
-            it64 = mrs_out["f64"]["iters"]
-            out["cpu_baseline"]["mrs_ms_per_iter"] = round(per_it, 3)
-            out["cpu_baseline"]["mrs_ms_to_tol_est"] = round(per_it * it64, 1)
-            out["cpu_baseline"]["mrs_sample"] = f"{k} oracle FP64 MRS iterations (one thread), scaled to {it64}"
+        out["cpu_baseline"] = cpu_baseline(args, oracle, synth, np, L, shift, mrs_out)
     print(json.dumps(out), flush=True)
     return 0
 

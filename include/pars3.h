@@ -151,10 +151,17 @@ void pars3_destroy(pars3_matrix *A);
 
 /* Reorders and splits on the GPU (Section 3.1.2: reverse Cuthill-McKee, then
  * the three-way split; both are integer work and bit-exact against the fixed
- * tie-break definition).  p == NULL selects the defaults.  Reverse
- * Cuthill-McKee runs once per handle; later calls with other parameters only
- * re-split and rebuild the layouts.  Synchronous (reads back the split sizes).
- * Errors: EINVAL for out-of-range parameters or w_in > t_out. */
+ * tie-break definition).  p == NULL: when a network is in use
+ * (pars3_model_use), the configuration it selects from the features of the
+ * reordered matrix (Section 3.1.2 leaves the outer bandwidth to be chosen from
+ * the bandwidth and density of the reordered matrix; as pars3_select with the
+ * network's stored grid), else the defaults.  Reverse Cuthill-McKee runs once
+ * per handle; later calls with other parameters only re-split and rebuild the
+ * layouts.  Also reserves 2 n x 64 bytes of device scratch for products in the
+ * caller's numbering (pars3_spmv with PARS3_ORDER_ORIGINAL, up to 8 FP64
+ * right-hand sides), so that pars3_spmv never allocates.  Synchronous (reads
+ * back the split sizes).  Errors: EINVAL for out-of-range parameters or
+ * w_in > t_out; ENOMEM. */
 pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *p, void *stream);
 
 /* y = shift*x + S*x  (the shifted skew-symmetric product; Section 1 and eqs.
@@ -168,6 +175,8 @@ pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *p, void *s
  * scatter are added).  x and y must not overlap and, when k > 1, must be
  * 16-byte aligned (rows are read and written as 16-byte vectors).
  * Asynchronous.  Errors:
+ * Neither allocates nor waits for the stream, so it may be captured in a
+ * hipGraph (in both orders).  Errors:
  * ESTATE before pars3_reorder or for a dtype mismatch; EINVAL otherwise. */
 pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x, void *y, int32_t k, int32_t vec_dtype,
                         int32_t order, void *stream);
@@ -285,9 +294,10 @@ pars3_status pars3_autotune(pars3_matrix *A, const pars3_split_params *grid, int
  *   f[31] share of 256-row tiles whose window (tile end - smallest column of
  *         the tile) holds at most 160 KiB of FP64 x and y (16 bytes a row)
  * Ratios with a zero denominator are 0; n = 0 gives all zeros.  Counts are
- * taken on the GPU; f (host, 32 doubles) is written on return (synchronous,
- * on the null stream).  Errors: ESTATE before pars3_reorder. */
-pars3_status pars3_features(const pars3_matrix *A, double *f);
+ * taken on the GPU, on `stream` (after the work already queued there); f
+ * (host, 32 doubles) is written on return (synchronous).  Errors: ESTATE
+ * before pars3_reorder; EINVAL for a NULL argument. */
+pars3_status pars3_features(const pars3_matrix *A, double *f, void *stream);
 
 /* MRS solver for (alpha*I + S) x = b (Section 1: the minimal-residual method
  * for shifted skew-symmetric systems that motivates the product; each
@@ -453,6 +463,34 @@ pars3_status pars3_mlp_select_rows(pars3_mlp *m, const float *X, int32_t rows, c
                                    void *stream);
 pars3_status pars3_select(pars3_matrix *A, pars3_mlp *m, const pars3_split_params *grid, int32_t ngrid,
                           int32_t *choice, void *stream);
+
+/* The configurations the network's outputs stand for (output g predicts
+ * grid[g]), kept with the network for pars3_select with grid = NULL, for
+ * pars3_model_save and for pars3_reorder(A, NULL) (Section 3.1.2: the split is
+ * a choice made from the reordered matrix).  set: ngrid must equal n_out
+ * (EINVAL).  get: *count receives the size; grid (may be NULL) receives up to
+ * cap entries (EINVAL when cap < size).  Host arrays. */
+pars3_status pars3_mlp_set_grid(pars3_mlp *m, const pars3_split_params *grid, int32_t ngrid);
+pars3_status pars3_mlp_get_grid(const pars3_mlp *m, pars3_split_params *grid, int32_t cap, int32_t *count);
+
+/* Trained selector on disk (a binary file, little-endian): the magic
+ * "PARS3MLP", format version 1 (uint32), int32 n_in, h1, h2, n_out, ngrid,
+ * ngrid x 6 int32 split parameters in pars3_split_params field order, the
+ * scaler (n_in float means, n_in float standard deviations), the packed
+ * weights (float, as pars3_mlp_get_params) and a 64-bit FNV-1a hash of every
+ * preceding byte.  save: needs a grid (ESTATE otherwise); EIO when the file
+ * cannot be written.  load: *out receives a new network (caller owns it;
+ * pars3_mlp_destroy) with weights, scaler and grid; Adam state zero; EIO for
+ * a missing, truncated or corrupted file, a bad magic, version or size.
+ * Synchronous. */
+pars3_status pars3_model_save(const pars3_mlp *m, const char *path);
+pars3_status pars3_model_load(const char *path, pars3_mlp **out);
+
+/* Sets the network that pars3_reorder(A, NULL, ...) consults, process-wide
+ * (NULL: none, the defaults apply).  The caller keeps ownership and keeps the
+ * network alive while it is in use; pars3_mlp_destroy of the network in use
+ * clears it.  ESTATE when the network has no grid. */
+pars3_status pars3_model_use(pars3_mlp *m);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *pars3_last_error(void);

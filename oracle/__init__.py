@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-CFLAGS = ["-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force: bool = False) -> str:
@@ -57,6 +57,8 @@ def _L():
             "or_full_csr": ([i32, _vp, _vp, _vp, d, _vp, _vp, _vp], i64),
             "or_full_csr_ex": ([i32, _vp, _vp, _vp, d, _vp, d, _vp, _vp, _vp], i64),
             "or_csr_spmv": ([i32, _vp, _vp, _vp, _vp, _vp], None),
+            "or_csr_spmv_par": ([i32, _vp, _vp, _vp, _vp, _vp], None),
+            "or_num_threads": ([], ctypes.c_int),
             "or_sss_spmv": ([i32, _vp, _vp, _vp, d, _vp, _vp], None),
             "or_sss_spmv_ex": ([i32, _vp, _vp, _vp, d, _vp, d, _vp, _vp], None),
             "or_round_f32": ([i64, _vp, _vp], None),
@@ -154,6 +156,22 @@ def csr_spmv(frow, fcol, fval, x) -> np.ndarray:
     if n > 0:
         _L().or_csr_spmv(n, _p(frow), _p(fcol), _p(fval), _p(x), _p(y))
     return y
+
+
+def csr_spmv_par(frow, fcol, fval, x) -> np.ndarray:
+    """csr_spmv with the rows shared among the host's threads (the same sums,
+    bit for bit): the all-core CPU baseline."""
+    n = frow.shape[0] - 1
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros(n, np.float64)
+    if n > 0:
+        _L().or_csr_spmv_par(n, _p(frow), _p(fcol), _p(fval), _p(x), _p(y))
+    return y
+
+
+def num_threads() -> int:
+    """Threads csr_spmv_par uses."""
+    return int(_L().or_num_threads())
 
 
 def spmv(L, alpha: float, x, diag=None, symmetric: bool = False) -> np.ndarray:

@@ -2,7 +2,8 @@
  * Oracle for the skew-symmetric SpMV path.
  *
  * TEST INFRASTRUCTURE ONLY.  Plain, slow, single-threaded host C that states
- * what the path computes.  Only the tests, the smoke check and the benchmark's
+ * what the path computes (or_csr_spmv_par alone shares its rows among the
+ * host's threads, for the all-core CPU baseline, with the same sums).  Only the tests, the smoke check and the benchmark's
  * CPU-baseline leg load it; the library never does, and it shares no code,
  * header or constant with the GPU path.  Built with -O2 -fno-fast-math
  * -ffp-contract=off so that every product and sum is rounded as written.
@@ -23,6 +24,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Input validation (storage of one triangle, Sections 1 and 3).
@@ -371,6 +375,29 @@ void or_csr_spmv(int32_t n, const int32_t *frow, const int32_t *fcol, const doub
   }
 }
 
+/* The same full-CSR product with the rows shared among the host's threads
+ * (OpenMP, static schedule).  Each row is still summed alone in ascending
+ * column order, so the result equals or_csr_spmv bit for bit; this is the
+ * all-core CPU baseline. */
+void or_csr_spmv_par(int32_t n, const int32_t *frow, const int32_t *fcol, const double *fval,
+                     const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; i++) {
+    double s = 0.0;
+    for (int32_t e = frow[i]; e < frow[i + 1]; e++) s += fval[e] * x[fcol[e]];
+    y[i] = s;
+  }
+}
+
+/* Threads the parallel product uses (OpenMP's limit for this process). */
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* Serial SSS skew SpMV (the paper's baseline, Section 3.1.1, adapted to skew
  * symmetry with the pair rule of eqs. (2)-(6)): y = alpha*x; then for every
  * stored l = l_ij in row order: y_i += l * x_j and y_j -= l * x_i. */
@@ -506,8 +533,23 @@ int or_mrs(int32_t n, const int32_t *rowptr, const int32_t *col, const double *v
     }
     if (it > maxit) it = maxit;
   }
-  /* true residual */
-  or_sss_spmv(n, rowptr, col, val, alpha, x, r);
+  /* true residual of the returned x, with the full-CSR product of
+   * alpha*I + S (the definition, not the recurrence) */
+  {
+    int64_t nnz = n > 0 ? rowptr[n] : 0;
+    size_t m = (size_t)(2 * nnz + n + 1);
+    int32_t *frow = (int32_t *)malloc((size_t)(n + 1) * sizeof(int32_t));
+    int32_t *fcol = (int32_t *)malloc(m * sizeof(int32_t));
+    double *fval = (double *)malloc(m * sizeof(double));
+    if (!frow || !fcol || !fval) {
+      free(frow); free(fcol); free(fval);
+      free(r); free(v); free(vp); free(w); free(p); free(p1); free(p2);
+      return 1;
+    }
+    or_full_csr(n, rowptr, col, val, alpha, frow, fcol, fval);
+    or_csr_spmv(n, frow, fcol, fval, x, r);
+    free(frow); free(fcol); free(fval);
+  }
   for (int32_t i = 0; i < n; i++) r[i] = b[i] - r[i];
   if (info) {
     info[0] = (double)it;

@@ -115,7 +115,7 @@ SIGNATURES = {
     "pars3_csr_size": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _st),
     "pars3_conflict_map": ([_vp, _i32, _vp, ctypes.POINTER(BlockConflicts), _vp], _st),
     "pars3_csr_destroy": ([_vp], None),
-    "pars3_features": ([_vp, _vp], _st),
+    "pars3_features": ([_vp, _vp, _vp], _st),
     "pars3_tune_grid_default": ([_i32, _vp, _i32, ctypes.POINTER(_i32)], _st),
     "pars3_autotune": ([_vp, _vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32), _vp], _st),
     "pars3_batch_create": ([_i32, _vp, ctypes.POINTER(_vp)], _st),
@@ -138,6 +138,11 @@ SIGNATURES = {
     "pars3_mlp_train": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, ctypes.c_float, ctypes.c_uint64, _vp, _vp], _st),
     "pars3_mlp_select_rows": ([_vp, _vp, _i32, _vp, _vp, _vp], _st),
     "pars3_select": ([_vp, _vp, _vp, _i32, ctypes.POINTER(_i32), _vp], _st),
+    "pars3_mlp_set_grid": ([_vp, _vp, _i32], _st),
+    "pars3_mlp_get_grid": ([_vp, _vp, _i32, ctypes.POINTER(_i32)], _st),
+    "pars3_model_save": ([_vp, ctypes.c_char_p], _st),
+    "pars3_model_load": ([ctypes.c_char_p, ctypes.POINTER(_vp)], _st),
+    "pars3_model_use": ([_vp], _st),
     "pars3_mrs_opts_default": ([ctypes.POINTER(MrsOpts)], None),
     "pars3_mrs_solve": ([_vp, _d, _vp, _vp, ctypes.POINTER(MrsOpts), ctypes.POINTER(MrsInfo), _vp], _st),
     "pars3_last_error": ([], ctypes.c_char_p),
@@ -377,9 +382,9 @@ def pars3_autotune(h, grid=None, k=1, reps=20, stream=None, value_dtype=F64):
     return res, best.value
 
 
-def pars3_features(h) -> np.ndarray:
+def pars3_features(h, stream=None) -> np.ndarray:
     f = np.zeros(32, np.float64)
-    _check(lib().pars3_features(h, _ptr(f)), "pars3_features")
+    _check(lib().pars3_features(h, _ptr(f), _stream(stream)), "pars3_features")
     return f
 
 
@@ -495,6 +500,39 @@ class MLP:
                                      float(lr), int(seed), _ptr(hist), _stream(stream)), "pars3_mlp_train")
         return hist[:epochs]
 
+    def set_grid(self, grid):
+        """The configurations the outputs stand for (a ctypes array of
+        SplitParams, as pars3_tune_grid_default returns)."""
+        _check(lib().pars3_mlp_set_grid(self.h, grid, len(grid)), "pars3_mlp_set_grid")
+
+    def get_grid(self):
+        cnt = _i32()
+        _check(lib().pars3_mlp_get_grid(self.h, None, 0, ctypes.byref(cnt)), "pars3_mlp_get_grid")
+        grid = (SplitParams * max(cnt.value, 1))()
+        _check(lib().pars3_mlp_get_grid(self.h, grid, cnt.value, ctypes.byref(cnt)), "pars3_mlp_get_grid")
+        return grid[:cnt.value]
+
+    def save(self, path):
+        _check(lib().pars3_model_save(self.h, os.fsencode(path)), "pars3_model_save")
+
+    @classmethod
+    def load(cls, path):
+        """A network read by pars3_model_load (weights, scaler and grid)."""
+        h = _vp()
+        _check(lib().pars3_model_load(os.fsencode(path), ctypes.byref(h)), "pars3_model_load")
+        m = cls.__new__(cls)
+        m.h = h
+        sz = (_i32 * 4)()
+        npar = _i64()
+        _check(lib().pars3_mlp_sizes(h, sz, ctypes.byref(npar)), "pars3_mlp_sizes")
+        m.sizes = tuple(int(v) for v in sz)
+        m.n_params = npar.value
+        return m
+
+    def use(self):
+        """Makes this network the one pars3_reorder(A, NULL) consults."""
+        _check(lib().pars3_model_use(self.h), "pars3_model_use")
+
     def select_rows(self, X, valid=None, stream=None):
         import torch
         choice = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
@@ -554,10 +592,17 @@ class Batch:
         return st, [i.as_dict() for i in infos]
 
 
-def pars3_select(h, mlp: MLP, grid, stream=None) -> int:
+def pars3_select(h, mlp: MLP, grid=None, stream=None) -> int:
+    """Selects and applies a configuration; grid None: the network's own."""
     c = _i32()
-    _check(lib().pars3_select(h, mlp.h, grid, len(grid), ctypes.byref(c), _stream(stream)), "pars3_select")
+    _check(lib().pars3_select(h, mlp.h, grid, len(grid) if grid is not None else 0, ctypes.byref(c),
+                              _stream(stream)), "pars3_select")
     return c.value
+
+
+def pars3_model_use(mlp: MLP | None):
+    """Sets (or with None clears) the network pars3_reorder(A, NULL) consults."""
+    _check(lib().pars3_model_use(mlp.h if mlp is not None else None), "pars3_model_use")
 
 
 # ------------------------------------------------------------------ convenience wrapper

@@ -601,7 +601,8 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
       infos[i].eta = std::fabs(hd[i].eta[hd[i].iter & 1]) / bn;
       infos[i].time_ms = ms;
     }
-    if (status != 0 && worst == 0) worst = status;
+    // worst first: NaN/Inf (3), then breakdown (2), then the iteration limit (1)
+    if (status != 0 && (worst == 0 || status > worst)) worst = status;
   }
   if (worst == 3) return fail(PARS3_ENAN, "batch mrs: NaN or Inf met");
   if (worst == 2) return fail(PARS3_EBREAKDOWN, "batch mrs: breakdown in at least one system");

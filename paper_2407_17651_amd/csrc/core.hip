@@ -150,6 +150,9 @@ static pars3_status check_params(const pars3_split_params &p) {
 extern "C" pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *pp, void *stream) {
   p3::clear_error();
   if (!A) return fail(PARS3_EINVAL, "reorder: NULL handle");
+  // no parameters: the selector's configuration when a network is in use
+  // (pars3_model_use), else the defaults
+  if (!pp && p3::has_selector()) return p3::reorder_selected(A, stream);
   pars3_split_params p;
   if (pp) p = *pp;
   else pars3_split_params_default(&p);
@@ -170,6 +173,14 @@ extern "C" pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params 
   p3::skew_shadow_free(A->shadow);  // built for the previous split
   A->shadow = nullptr;
   P3_TRY(p3::split_and_layout(A, p, s));
+  // scratch of products in the caller's numbering (up to 8 FP64 right-hand
+  // sides), reserved here so that pars3_spmv never allocates
+  const size_t rbytes = (size_t)A->n * p3::ORIG_MAX_ROW_BYTES;
+  if (A->xr.n < rbytes || A->yr.n < rbytes) {
+    P3_HIP(hipStreamSynchronize(s));
+    P3_HIP(A->xr.alloc(rbytes));
+    P3_HIP(A->yr.alloc(rbytes));
+  }
   P3_HIP(hipStreamSynchronize(s));
   A->split_done = true;
   return PARS3_OK;
@@ -196,11 +207,8 @@ extern "C" pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x,
   if (overlap(x, y, bytes)) return fail(PARS3_EINVAL, "spmv: x and y overlap");
   hipStream_t s = (hipStream_t)stream;
   if (order == PARS3_ORDER_RCM) return p3::spmv_rcm(A, shift, x, y, k, vec_dtype, s);
-  if (A->xr.n < bytes) {
-    P3_HIP(hipStreamSynchronize(s));
-    P3_HIP(A->xr.alloc(bytes));
-    P3_HIP(A->yr.alloc(bytes));
-  }
+  // the scratch was reserved by pars3_reorder (no allocation or wait here)
+  if (A->xr.n < bytes || A->yr.n < bytes) return fail(PARS3_ESTATE, "spmv: no scratch for the caller's numbering");
   P3_TRY(p3::prof_mark(A, p3::PROF_FIXUP, 0, s));
   P3_TRY(p3::gather_rows(x, A->xr.p, A->perm.p, A->n, k, elem, s));
   P3_TRY(p3::prof_mark(A, p3::PROF_FIXUP, 1, s));

@@ -148,6 +148,38 @@ static pars3_status csr_launch(pars3_csr *C, const V *val, X shift, const X *x, 
 
 using p3::fail;
 
+static pars3_status rocsparse_prepare(pars3_csr *C, const void *x, void *y, hipStream_t s) {
+  const bool f64 = C->vdtype == PARS3_F64;
+  const rocsparse_datatype dt = f64 ? rocsparse_datatype_f64_r : rocsparse_datatype_f32_r;
+  if (!C->rh) P3_RS(rocsparse_create_handle(&C->rh));
+  P3_RS(rocsparse_set_stream(C->rh, s));
+  if (!C->mat)
+    P3_RS(rocsparse_create_csr_descr(&C->mat, C->n, C->n, C->nnz, C->rowptr.p, C->col.p,
+                                     f64 ? (void *)C->v64.p : (void *)C->v32.p, rocsparse_indextype_i32,
+                                     rocsparse_indextype_i32, rocsparse_index_base_zero, dt));
+  rocsparse_dnvec_descr dx = nullptr, dy = nullptr;
+  P3_RS(rocsparse_create_dnvec_descr(&dx, C->n, const_cast<void *>(x), dt));
+  P3_RS(rocsparse_create_dnvec_descr(&dy, C->n, y, dt));
+  const double one64 = 1.0, zero64 = 0.0;
+  const float one32 = 1.f, zero32 = 0.f;
+  const void *one = f64 ? (const void *)&one64 : (const void *)&one32;
+  const void *zero = f64 ? (const void *)&zero64 : (const void *)&zero32;
+  rocsparse_status r = rocsparse_spmv(C->rh, rocsparse_operation_none, one, C->mat, dx, zero, dy, dt,
+                                      rocsparse_spmv_alg_default, rocsparse_spmv_stage_buffer_size, &C->bufsz, nullptr);
+  if (r == rocsparse_status_success) {
+    hipError_t e = C->buf.alloc(C->bufsz ? C->bufsz : 1);
+    if (e != hipSuccess) r = rocsparse_status_memory_error;
+  }
+  if (r == rocsparse_status_success)
+    r = rocsparse_spmv(C->rh, rocsparse_operation_none, one, C->mat, dx, zero, dy, dt, rocsparse_spmv_alg_default,
+                       rocsparse_spmv_stage_preprocess, &C->bufsz, C->buf.p);
+  rocsparse_destroy_dnvec_descr(dx);
+  rocsparse_destroy_dnvec_descr(dy);
+  if (r != rocsparse_status_success) return fail(PARS3_EHIP, "csr_spmv: rocsparse preprocessing failed (%d)", (int)r);
+  C->rs_ready = true;
+  return PARS3_OK;
+}
+
 extern "C" pars3_status pars3_csr_create(const pars3_matrix *A, int32_t order, int32_t value_dtype, pars3_csr **out) {
   if (!A || !out) return fail(PARS3_EINVAL, "csr_create: NULL argument");
   *out = nullptr;
@@ -210,6 +242,17 @@ extern "C" pars3_status pars3_csr_create(const pars3_matrix *A, int32_t order, i
     int lanes = 1;
     while (lanes < 64 && lanes * 1.5 < mean) lanes *= 2;
     C->lanes = lanes;
+    // rocSPARSE's analysis of the matrix (handle, buffer, preprocessing) is
+    // done here, once, so that a product never runs setup work; its vector
+    // descriptors point at scratch vectors that are freed afterwards (the
+    // analysis depends on the matrix only)
+    if (n > 0) {
+      p3::dbuf<double> tx, ty;
+      P3_HIP(tx.alloc(n));
+      P3_HIP(ty.alloc(n));
+      P3_TRY(rocsparse_prepare(C, tx.p, ty.p, s));
+      P3_HIP(hipStreamSynchronize(s));
+    }
     return PARS3_OK;
   };
   pars3_status st = run();
@@ -222,38 +265,6 @@ extern "C" pars3_status pars3_csr_create(const pars3_matrix *A, int32_t order, i
 }
 
 extern "C" void pars3_csr_destroy(pars3_csr *C) { delete C; }
-
-static pars3_status rocsparse_prepare(pars3_csr *C, const void *x, void *y, hipStream_t s) {
-  const bool f64 = C->vdtype == PARS3_F64;
-  const rocsparse_datatype dt = f64 ? rocsparse_datatype_f64_r : rocsparse_datatype_f32_r;
-  if (!C->rh) P3_RS(rocsparse_create_handle(&C->rh));
-  P3_RS(rocsparse_set_stream(C->rh, s));
-  if (!C->mat)
-    P3_RS(rocsparse_create_csr_descr(&C->mat, C->n, C->n, C->nnz, C->rowptr.p, C->col.p,
-                                     f64 ? (void *)C->v64.p : (void *)C->v32.p, rocsparse_indextype_i32,
-                                     rocsparse_indextype_i32, rocsparse_index_base_zero, dt));
-  rocsparse_dnvec_descr dx = nullptr, dy = nullptr;
-  P3_RS(rocsparse_create_dnvec_descr(&dx, C->n, const_cast<void *>(x), dt));
-  P3_RS(rocsparse_create_dnvec_descr(&dy, C->n, y, dt));
-  const double one64 = 1.0, zero64 = 0.0;
-  const float one32 = 1.f, zero32 = 0.f;
-  const void *one = f64 ? (const void *)&one64 : (const void *)&one32;
-  const void *zero = f64 ? (const void *)&zero64 : (const void *)&zero32;
-  rocsparse_status r = rocsparse_spmv(C->rh, rocsparse_operation_none, one, C->mat, dx, zero, dy, dt,
-                                      rocsparse_spmv_alg_default, rocsparse_spmv_stage_buffer_size, &C->bufsz, nullptr);
-  if (r == rocsparse_status_success) {
-    hipError_t e = C->buf.alloc(C->bufsz ? C->bufsz : 1);
-    if (e != hipSuccess) r = rocsparse_status_memory_error;
-  }
-  if (r == rocsparse_status_success)
-    r = rocsparse_spmv(C->rh, rocsparse_operation_none, one, C->mat, dx, zero, dy, dt, rocsparse_spmv_alg_default,
-                       rocsparse_spmv_stage_preprocess, &C->bufsz, C->buf.p);
-  rocsparse_destroy_dnvec_descr(dx);
-  rocsparse_destroy_dnvec_descr(dy);
-  if (r != rocsparse_status_success) return fail(PARS3_EHIP, "csr_spmv: rocsparse preprocessing failed (%d)", (int)r);
-  C->rs_ready = true;
-  return PARS3_OK;
-}
 
 extern "C" pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x, void *y, int32_t engine,
                                        void *stream) {
@@ -268,7 +279,7 @@ extern "C" pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x
     return p3::csr_launch<float, float>(C, C->v32.p, (float)shift, (const float *)x, (float *)y, s);
   }
   if (shift != 0.0) return fail(PARS3_EINVAL, "csr_spmv: the rocSPARSE engine computes S*x only (shift must be 0)");
-  if (!C->rs_ready) P3_TRY(rocsparse_prepare(C, x, y, s));
+  if (!C->rs_ready) return fail(PARS3_ESTATE, "csr_spmv: rocSPARSE was not prepared");
   P3_RS(rocsparse_set_stream(C->rh, s));
   const rocsparse_datatype dt = f64 ? rocsparse_datatype_f64_r : rocsparse_datatype_f32_r;
   rocsparse_dnvec_descr dx = nullptr, dy = nullptr;

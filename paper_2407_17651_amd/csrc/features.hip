@@ -126,7 +126,7 @@ __global__ void k_row_of_entry(const int32_t *__restrict__ rp, int32_t n, int32_
 
 using p3::fail;
 
-extern "C" pars3_status pars3_features(const pars3_matrix *A, double *f) {
+extern "C" pars3_status pars3_features(const pars3_matrix *A, double *f, void *stream) {
   using namespace p3;
   if (!A || !f) return fail(PARS3_EINVAL, "features: NULL argument");
   if (!A->perm_done) return fail(PARS3_ESTATE, "features: call pars3_reorder first");
@@ -134,7 +134,7 @@ extern "C" pars3_status pars3_features(const pars3_matrix *A, double *f) {
   const int32_t n = (int32_t)A->n;
   const int64_t nnz = A->nnz;
   if (n <= 0) return PARS3_OK;
-  hipStream_t s = nullptr;
+  hipStream_t s = (hipStream_t)stream;
   dbuf<feat_counts> dfc;
   dbuf<uint64_t> k0, k1;
   dbuf<uint32_t> v0, v1;

@@ -43,10 +43,16 @@ struct dbuf {
   dbuf(const dbuf &) = delete;
   dbuf &operator=(const dbuf &) = delete;
   ~dbuf() { release(); }
+  // On failure the buffer stays empty (p == nullptr, n == 0), so a size check
+  // of a later call never mistakes a failed allocation for a usable one.
   hipError_t alloc(size_t m) {
     release();
+    void *q = nullptr;
+    const hipError_t e = hipMalloc(&q, (m ? m : 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    p = (T *)q;
     n = m;
-    return hipMalloc((void **)&p, (m ? m : 1) * sizeof(T));
+    return e;
   }
   void release() {
     if (p) (void)hipFree(p);
@@ -145,6 +151,7 @@ pars3_status iota_i32(int32_t *p, int64_t m, hipStream_t s);
 constexpr int CHUNKS_FIXED = 32;          // fixed chunk slots per tile (4 wavefronts x 8)
 constexpr uint32_t CHUNK_EMPTY = 0xffffffffu;
 constexpr int ENT16_MAX_LGT = 8;          // tiles of at most 256 rows store 16-bit entry words
+constexpr size_t ORIG_MAX_ROW_BYTES = 8 * sizeof(double);  // 8 FP64 right-hand sides
 // One SpMV layout: the three parts of the split arranged for the kernel.
 struct layout {
   int32_t T = 256, lgT = 8, w_in = 0, t_out = 0;
@@ -224,7 +231,9 @@ struct pars3_matrix {
   pars3_split_params params{};
   p3::layout lay;
   bool has_f64 = false, has_f32 = false, has_bf16 = false;
-  // scratch for products in the caller's numbering
+  // scratch for products in the caller's numbering: x and y in the reordered
+  // numbering, n rows of up to ORIG_MAX_ROW_BYTES each, reserved by
+  // pars3_reorder so that pars3_spmv never allocates or synchronises
   p3::dbuf<char> xr, yr;
   // solver stream and workspace (mrs.hip), created on first use
   hipStream_t solver_stream = nullptr;
@@ -388,6 +397,12 @@ pars3_status prof_mark(pars3_matrix *A, int cls, int stop, hipStream_t s);
 pars3_status spmv_rcm(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, hipStream_t s);
 pars3_status gather_rows(const void *src, void *dst, const int32_t *idx, int64_t n, int k, size_t elem,
                          hipStream_t s);
+// mlp.hip / tune.hip: the configuration grid of a network, the process-wide
+// selector that pars3_reorder(A, NULL) consults, and its use
+const std::vector<pars3_split_params> &mlp_grid(const pars3_mlp *m);
+void forget_selector(const pars3_mlp *m);
+bool has_selector();
+pars3_status reorder_selected(pars3_matrix *A, void *stream);
 pars3_status scatter_rows(const void *src, void *dst, const int32_t *idx, int64_t n, int k, size_t elem,
                           hipStream_t s);
 }  // namespace p3

@@ -8,7 +8,10 @@
 // Weights are stored input-major (W has shape [fan_in, fan_out]) and packed
 // W1, b1, W2, b2, W3, b3 in one device array.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -25,6 +28,9 @@ struct pars3_mlp {
   p3::dbuf<float> Xs, Ts, Ms, Z1, H1, Z2, H2, Out, GOut, GH2, GH1;
   p3::dbuf<double> red;  // loss and mask count
   p3::dbuf<int32_t> idx;
+  // the configurations the outputs stand for (output g predicts grid[g]);
+  // empty until pars3_mlp_set_grid or pars3_model_load
+  std::vector<pars3_split_params> grid;
 };
 
 namespace p3 {
@@ -331,7 +337,11 @@ extern "C" pars3_status pars3_mlp_create(int32_t n_in, int32_t h1, int32_t h2, i
   return fin(PARS3_OK);
 }
 
-extern "C" void pars3_mlp_destroy(pars3_mlp *m) { delete m; }
+extern "C" void pars3_mlp_destroy(pars3_mlp *m) {
+  if (!m) return;
+  p3::forget_selector(m);
+  delete m;
+}
 
 extern "C" pars3_status pars3_mlp_sizes(const pars3_mlp *m, int32_t *sizes4, int64_t *n_params) {
   if (!m) return fail(PARS3_EINVAL, "mlp: NULL handle");
@@ -489,5 +499,151 @@ extern "C" pars3_status pars3_mlp_select_rows(pars3_mlp *m, const float *X, int3
   P3_TRY(forward(m, rows, s));
   k_argmin<<<g1(rows), 256, 0, s>>>(m->Out.p, valid, rows, m->n_out, choice);
   P3_LAUNCHED();
+  return PARS3_OK;
+}
+
+// ------------------------------------------------------------ grid and files
+namespace p3 {
+const std::vector<pars3_split_params> &mlp_grid(const pars3_mlp *m) { return m->grid; }
+}  // namespace p3
+
+extern "C" pars3_status pars3_mlp_set_grid(pars3_mlp *m, const pars3_split_params *grid, int32_t ngrid) {
+  if (!m || !grid) return fail(PARS3_EINVAL, "mlp: NULL argument");
+  if (ngrid != m->n_out) return fail(PARS3_EINVAL, "mlp: the grid has %d entries, the network %d outputs", ngrid, m->n_out);
+  m->grid.assign(grid, grid + ngrid);
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_mlp_get_grid(const pars3_mlp *m, pars3_split_params *grid, int32_t cap, int32_t *count) {
+  if (!m || !count) return fail(PARS3_EINVAL, "mlp: NULL argument");
+  *count = (int32_t)m->grid.size();
+  if (!grid) return PARS3_OK;
+  if (cap < *count) return fail(PARS3_EINVAL, "mlp: grid capacity %d < %d", cap, *count);
+  std::copy(m->grid.begin(), m->grid.end(), grid);
+  return PARS3_OK;
+}
+
+// Model file: little-endian, in this order
+//   char[8]  magic "PARS3MLP"
+//   uint32   format version (1)
+//   int32    n_in, h1, h2, n_out, ngrid (= n_out)
+//   int32    ngrid x 6 split parameters (w_in, t_out, tile_rows, value_dtype,
+//            keep_fp64, permute)
+//   float    n_in feature means, n_in feature standard deviations
+//   float    n_params weights packed W1, b1, W2, b2, W3, b3
+//   uint64   FNV-1a hash of every byte above
+namespace {
+constexpr char kMagic[8] = {'P', 'A', 'R', 'S', '3', 'M', 'L', 'P'};
+constexpr uint32_t kVersion = 1;
+
+struct fnv_writer {
+  FILE *f;
+  uint64_t h = 1469598103934665603ull;
+  bool ok = true;
+  void put(const void *p, size_t bytes) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < bytes; i++) h = (h ^ c[i]) * 1099511628211ull;
+    ok = ok && fwrite(p, 1, bytes, f) == bytes;
+  }
+};
+struct fnv_reader {
+  FILE *f;
+  uint64_t h = 1469598103934665603ull;
+  bool ok = true;
+  void get(void *p, size_t bytes) {
+    ok = ok && fread(p, 1, bytes, f) == bytes;
+    if (!ok) return;
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < bytes; i++) h = (h ^ c[i]) * 1099511628211ull;
+  }
+};
+}  // namespace
+
+extern "C" pars3_status pars3_model_save(const pars3_mlp *m, const char *path) {
+  if (!m || !path) return fail(PARS3_EINVAL, "model_save: NULL argument");
+  if ((int32_t)m->grid.size() != m->n_out)
+    return fail(PARS3_ESTATE, "model_save: the network has no configuration grid (pars3_mlp_set_grid)");
+  std::vector<float> P(m->np), mean(m->n_in), stdv(m->n_in);
+  P3_TRY(copy_host(P.data(), m->P.p, m->np * sizeof(float), hipMemcpyDeviceToHost));
+  P3_TRY(copy_host(mean.data(), m->mean.p, m->n_in * sizeof(float), hipMemcpyDeviceToHost));
+  P3_TRY(copy_host(stdv.data(), m->stdv.p, m->n_in * sizeof(float), hipMemcpyDeviceToHost));
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(PARS3_EIO, "model_save: cannot open %s for writing", path);
+  fnv_writer w{f};
+  w.put(kMagic, 8);
+  w.put(&kVersion, 4);
+  const int32_t hdr[5] = {m->n_in, m->h1, m->h2, m->n_out, (int32_t)m->grid.size()};
+  w.put(hdr, sizeof(hdr));
+  for (const pars3_split_params &g : m->grid) {
+    const int32_t v[6] = {g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute};
+    w.put(v, sizeof(v));
+  }
+  w.put(mean.data(), mean.size() * sizeof(float));
+  w.put(stdv.data(), stdv.size() * sizeof(float));
+  w.put(P.data(), P.size() * sizeof(float));
+  const uint64_t h = w.h;
+  const bool ok = w.ok && std::fwrite(&h, 1, 8, f) == 8;
+  if (std::fclose(f) != 0 || !ok) return fail(PARS3_EIO, "model_save: write to %s failed", path);
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_model_load(const char *path, pars3_mlp **out) {
+  if (!path || !out) return fail(PARS3_EINVAL, "model_load: NULL argument");
+  *out = nullptr;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(PARS3_EIO, "model_load: cannot open %s", path);
+  fnv_reader r{f};
+  char magic[8];
+  uint32_t ver = 0;
+  int32_t hdr[5] = {0, 0, 0, 0, 0};
+  r.get(magic, 8);
+  r.get(&ver, 4);
+  r.get(hdr, sizeof(hdr));
+  auto bad = [&](const char *what) {
+    std::fclose(f);
+    return fail(PARS3_EIO, "model_load: %s: %s", path, what);
+  };
+  if (!r.ok) return bad("truncated header");
+  if (std::memcmp(magic, kMagic, 8) != 0) return bad("not a model file");
+  if (ver != kVersion) return bad("unknown format version");
+  for (int k = 0; k < 4; k++)
+    if (hdr[k] < 1 || hdr[k] > 4096) return bad("layer size out of range");
+  if (hdr[4] != hdr[3]) return bad("grid size differs from the output count");
+  std::vector<pars3_split_params> grid(hdr[4]);
+  for (auto &g : grid) {
+    int32_t v[6];
+    r.get(v, sizeof(v));
+    g.w_in = v[0];
+    g.t_out = v[1];
+    g.tile_rows = v[2];
+    g.value_dtype = v[3];
+    g.keep_fp64 = v[4];
+    g.permute = v[5];
+  }
+  const int64_t np = (int64_t)hdr[0] * hdr[1] + hdr[1] + (int64_t)hdr[1] * hdr[2] + hdr[2] +
+                     (int64_t)hdr[2] * hdr[3] + hdr[3];
+  std::vector<float> mean(hdr[0]), stdv(hdr[0]), P(np);
+  r.get(mean.data(), mean.size() * sizeof(float));
+  r.get(stdv.data(), stdv.size() * sizeof(float));
+  r.get(P.data(), P.size() * sizeof(float));
+  const uint64_t want = r.h;
+  uint64_t got = 0;
+  const bool tail = r.ok && std::fread(&got, 1, 8, f) == 8;
+  char extra;
+  const bool at_end = std::fread(&extra, 1, 1, f) == 0;
+  std::fclose(f);
+  if (!r.ok || !tail) return fail(PARS3_EIO, "model_load: %s: truncated", path);
+  if (got != want) return fail(PARS3_EIO, "model_load: %s: checksum mismatch", path);
+  if (!at_end) return fail(PARS3_EIO, "model_load: %s: trailing bytes", path);
+  pars3_mlp *m = nullptr;
+  P3_TRY(pars3_mlp_create(hdr[0], hdr[1], hdr[2], hdr[3], 1, &m));
+  pars3_status st = pars3_mlp_set_params(m, P.data());
+  if (st == PARS3_OK) st = pars3_mlp_set_scaler(m, mean.data(), stdv.data());
+  if (st == PARS3_OK) st = pars3_mlp_set_grid(m, grid.data(), (int32_t)grid.size());
+  if (st != PARS3_OK) {
+    pars3_mlp_destroy(m);
+    return st;
+  }
+  *out = m;
   return PARS3_OK;
 }

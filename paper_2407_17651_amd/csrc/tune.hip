@@ -7,6 +7,7 @@
 // configuration is applied again at the end.  The table of timings is the
 // training record of the learned selector.
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "internal.h"
@@ -139,7 +140,14 @@ extern "C" pars3_status pars3_autotune(pars3_matrix *A, const pars3_split_params
 extern "C" pars3_status pars3_select(pars3_matrix *A, pars3_mlp *m, const pars3_split_params *grid, int32_t ngrid,
                                      int32_t *choice, void *stream) {
   using namespace p3;
-  if (!A || !m || !grid || ngrid < 1) return fail(PARS3_EINVAL, "select: NULL or empty argument");
+  if (!A || !m) return fail(PARS3_EINVAL, "select: NULL argument");
+  if (!grid) {  // the grid stored with the network
+    const std::vector<pars3_split_params> &g = mlp_grid(m);
+    if (g.empty()) return fail(PARS3_ESTATE, "select: no grid given and none stored with the network");
+    grid = g.data();
+    ngrid = (int32_t)g.size();
+  }
+  if (ngrid < 1) return fail(PARS3_EINVAL, "select: empty grid");
   int32_t sz[4];
   P3_TRY(pars3_mlp_sizes(m, sz, nullptr));
   if (sz[0] != 32 || sz[3] != ngrid)
@@ -154,7 +162,7 @@ extern "C" pars3_status pars3_select(pars3_matrix *A, pars3_mlp *m, const pars3_
     P3_TRY(pars3_reorder(A, &p0, stream));
   }
   double f[32];
-  P3_TRY(pars3_features(A, f));
+  P3_TRY(pars3_features(A, f, stream));
   float ff[32];
   for (int k = 0; k < 32; k++) ff[k] = (float)f[k];
   dbuf<float> xd;
@@ -176,4 +184,31 @@ extern "C" pars3_status pars3_select(pars3_matrix *A, pars3_mlp *m, const pars3_
   }
   const pars3_split_params p = resolve(grid[c], A->beta);
   return pars3_reorder(A, &p, stream);
+}
+
+// ------------------------------------------------------------ default selector
+// The network that pars3_reorder(A, NULL, ...) consults.  The caller owns it;
+// pars3_mlp_destroy of the network in use clears it.
+namespace p3 {
+static std::atomic<pars3_mlp *> g_selector{nullptr};
+
+void forget_selector(const pars3_mlp *m) {
+  pars3_mlp *cur = const_cast<pars3_mlp *>(m);
+  g_selector.compare_exchange_strong(cur, nullptr);
+}
+
+bool has_selector() { return g_selector.load() != nullptr; }
+
+pars3_status reorder_selected(pars3_matrix *A, void *stream) {
+  pars3_mlp *m = g_selector.load();
+  if (!m) return fail(PARS3_ESTATE, "reorder: no selector in use");
+  return pars3_select(A, m, nullptr, 0, nullptr, stream);
+}
+}  // namespace p3
+
+extern "C" pars3_status pars3_model_use(pars3_mlp *m) {
+  if (m && (int32_t)p3::mlp_grid(m).size() < 1)
+    return fail(PARS3_ESTATE, "model_use: the network has no configuration grid (pars3_mlp_set_grid)");
+  p3::g_selector.store(m);
+  return PARS3_OK;
 }

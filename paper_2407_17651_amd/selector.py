@@ -196,6 +196,7 @@ def load_trained(p3, path: str = WEIGHTS, value_dtype=None):
     grid = p3.pars3_tune_grid_default(p3.F32 if value_dtype is None else value_dtype)
     if len(grid) != sizes[3]:
         raise ValueError("the saved network does not match the default grid")
+    net.set_grid(grid)
     return net, grid
 
 

@@ -47,3 +47,35 @@ def test_features_before_reorder_is_an_error():
     with pytest.raises(p3.Pars3Error) as e:
         M.features()
     assert e.value.status == p3.ESTATE
+
+
+def _rows_lower(n, rc):
+    rowptr = np.zeros(n + 1, np.int32)
+    for r, _ in rc:
+        rowptr[r + 1:] += 1
+    order = sorted(rc)
+    return synth.Lower(n, rowptr, np.array([c for _, c in order], np.int32), np.ones(len(rc)))
+
+
+@pytest.mark.parametrize("name,L", [
+    # the 160 KiB window: exactly full, 16 bytes over, exactly full only with the last tile clipped
+    ("window_boundaries", _rows_lower(20600, [(10300, 256), (15400, 15616 - 10241), (20590, 20600 - 10240)])),
+    # distances exactly at beta/2, 3 beta/4 and 9 beta/10 (beta = 20)
+    ("distance_thresholds", _rows_lower(40, [(30, 10), (31, 21), (32, 17), (33, 15), (34, 23), (35, 19), (36, 17)])),
+])
+def test_features_at_their_boundaries_bit_exact(name, L):
+    """The hand-built boundary cases of the oracle's pins, in the given
+    order (no reordering), bit for bit."""
+    M = p3.Matrix(L).reorder(permute=0)
+    got, want = M.features(), oracle.features(L)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), np.flatnonzero(got != want)
+
+
+def test_features_on_a_stream():
+    """pars3_features on a side stream, after work queued there."""
+    import torch
+    L = synth.grid3d(20, 3, "normal")
+    M = p3.Matrix(L).reorder()
+    s = torch.cuda.Stream()
+    got = p3.pars3_features(M.h, s)
+    assert np.array_equal(got, oracle.features(oracle.permute(L, oracle.rcm(L))))

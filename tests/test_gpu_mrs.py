@@ -226,3 +226,30 @@ def test_empty_matrix():
     st, info, _ = M.mrs(1.0, torch.zeros(0, dtype=torch.float64, device="cuda"),
                         torch.zeros(0, dtype=torch.float64, device="cuda"))
     assert st == p3.OK and info["iters"] == 0
+
+
+@pytest.mark.parametrize("precision", [p3.F64, p3.F32, p3.BF16])
+def test_nan_in_rhs_reports_enan(precision):
+    """A NaN in b makes ||b|| and every iterate NaN: the solver stops and
+    returns ENAN (status 3) instead of iterating to the limit."""
+    L = synth.grid2d(30, 2)
+    M = p3.Matrix(L).reorder(value_dtype=precision, keep_fp64=int(precision != p3.F64))
+    b = synth.vector(L.n, 5)
+    b[17] = np.nan
+    st, info, _, _ = solve(M, 0.5, b, tol=1e-10, maxit=300, precision=precision)
+    assert st == p3.ENAN and info["status"] == 3
+    assert info["iters"] < 300
+
+
+@pytest.mark.parametrize("precision", [p3.F64, p3.F32])
+def test_inf_matrix_value_reports_enan(precision):
+    """An infinite stored value makes the first product, hence the Lanczos
+    norm, infinite or NaN: ENAN."""
+    L = synth.grid2d(30, 3)
+    val = L.val.copy()
+    val[40] = np.inf
+    Li = synth.Lower(L.n, L.rowptr, L.col, val)
+    M = p3.Matrix(Li).reorder(value_dtype=precision, keep_fp64=int(precision != p3.F64))
+    b = synth.vector(L.n, 6)
+    st, info, _, _ = solve(M, 0.5, b, tol=1e-10, maxit=300, precision=precision)
+    assert st == p3.ENAN and info["status"] == 3

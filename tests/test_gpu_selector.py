@@ -50,3 +50,77 @@ def test_saved_network_selects_well(data):
     paper = int(np.flatnonzero((g[:, 0] == 256) & (g[:, 1] == 0) & (g[:, 2] == -1))[0])
     rp = selector.regrets(data["times_us"][te], np.full(len(choice), paper))
     assert r.mean() < rp.mean()
+
+
+def _grid_tuple(g):
+    return (g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute)
+
+
+def test_model_file_round_trip_and_selection_through_the_c_abi(tmp_path):
+    """pars3_model_save writes the trained network, pars3_model_load reads it
+    back (weights, scaler and grid bit for bit), and the reloaded network
+    selects through pars3_select with its stored grid exactly as the
+    original does."""
+    import synth
+    net, grid = selector.load_trained(p3)
+    path = str(tmp_path / "selector.p3mlp")
+    net.save(path)
+    back = p3.MLP.load(path)
+    assert back.sizes == net.sizes
+    for k, v in net.get_params().items():
+        assert np.array_equal(back.get_params()[k], v), k
+    for a, b in zip(net.get_scaler(), back.get_scaler()):
+        assert np.array_equal(a, b)
+    assert [_grid_tuple(g) for g in back.get_grid()] == [_grid_tuple(g) for g in grid]
+    for L in (synth.grid3d(30, 3), synth.rgg2d(40000, 16.0, 9), synth.chung_lu(20000, 16.0, 2.5, 2)):
+        A = p3.Matrix(L).reorder(value_dtype=p3.F32)
+        B = p3.Matrix(L).reorder(value_dtype=p3.F32)
+        c0 = p3.pars3_select(A.h, net, grid)
+        c1 = p3.pars3_select(B.h, back)  # the grid stored in the file
+        assert c0 == c1
+        assert A.info() == B.info()
+
+
+def test_reorder_without_parameters_uses_the_network_in_use(tmp_path):
+    """pars3_reorder(A, NULL) applies the configuration that the network in
+    use (pars3_model_use) selects, and the defaults again once it is cleared
+    or destroyed."""
+    import synth
+    net, grid = selector.load_trained(p3)
+    path = str(tmp_path / "m.p3mlp")
+    net.save(path)
+    m = p3.MLP.load(path)
+    L = synth.rgg2d(50000, 16.0, 21)
+    ref = p3.Matrix(L)
+    c = p3.pars3_select(ref.h, m)
+    want = ref.info()
+    try:
+        m.use()
+        A = p3.Matrix(L)
+        p3.pars3_reorder(A.h, None)
+        assert A.info() == want
+        g = grid[c]
+        assert want["tile_rows"] == g.tile_rows and want["value_dtype"] == g.value_dtype
+    finally:
+        p3.pars3_model_use(None)
+    D = p3.Matrix(L)
+    p3.pars3_reorder(D.h, None)
+    info = D.info()
+    assert info["tile_rows"] == 256 and info["w_in"] == 0 and info["t_out"] == max(info["beta"] - 3, 0)
+    assert info["value_dtype"] == p3.F64
+    # destroying the network in use clears it too
+    m.use()
+    m.close()
+    E = p3.Matrix(L)
+    p3.pars3_reorder(E.h, None)
+    assert E.info() == info
+
+
+def test_model_save_needs_a_grid(tmp_path):
+    net = p3.MLP(32, 8, 8, 40, seed=3)
+    with pytest.raises(p3.Pars3Error) as e:
+        net.save(str(tmp_path / "x.p3mlp"))
+    assert e.value.status == p3.ESTATE
+    with pytest.raises(p3.Pars3Error) as e:
+        net.use()
+    assert e.value.status == p3.ESTATE

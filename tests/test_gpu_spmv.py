@@ -178,6 +178,49 @@ def test_workload1_full_size_fp64():
     print(f"[gpu] workload1 fp64 rel err {err:.3e}", flush=True)
 
 
+@pytest.mark.parametrize("value_dtype", [p3.F32, p3.BF16])
+def test_workload1_full_size_low_precision(value_dtype):
+    """The benchmark workload with FP32 and BF16 stored values (FP32 vectors),
+    every output against the oracle run on the same rounded values and
+    vectors."""
+    L = synth.workload(1)
+    print(f"[gpu] spmv workload1 dtype={value_dtype}", flush=True)
+    M, err = check_product(L, shift=0.5, value_dtype=value_dtype, seed=1101)
+    print(f"[gpu] workload1 dtype={value_dtype} rel err {err:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("k", [1, 8])
+def test_original_order_in_a_graph(k):
+    """A product in the caller's numbering (gather, product, scatter) captured
+    in a graph: the call neither allocates nor waits, so capture succeeds on
+    a handle's first such call, and every replay, with eager work and
+    synchronisations between them, equals the eager result and the oracle."""
+    L = synth.rgg2d(12000, 10.0, 31)
+    M = p3.Matrix(L).reorder()
+    X = synth.vector(L.n, 9, k) if k > 1 else synth.vector(L.n, 9)
+    x = to_dev(X)
+    y = torch.full_like(x, float("nan"))
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            p3.pars3_spmv(M.h, 0.75, x, y, k, p3.F64, p3.ORDER_ORIGINAL)
+    torch.cuda.synchronize()
+    want = oracle.spmv(L, 0.75, X)
+    eager = gpu_spmv(M, 0.75, X, p3.F64, p3.ORDER_ORIGINAL)
+    assert rel_inf(eager, want) <= 1e-12
+    for r in range(4):
+        y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+        # the LDS sums may add in another order from run to run
+        assert rel_inf(got, eager) <= 1e-12 and rel_inf(got, want) <= 1e-12, r
+        _ = gpu_spmv(M, -1.0, X, p3.F64, p3.ORDER_RCM)  # eager work between replays
+
+
 @pytest.fixture(scope="module")
 def workload2():
     L = synth.workload(2)

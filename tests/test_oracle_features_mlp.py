@@ -97,3 +97,44 @@ def test_adam_first_step_is_signed_learning_rate():
     P, m, v = mlp.adam_step(p, g, z, z, 1, lr=1e-2, eps=0.0)
     for k in mlp.NAMES:
         assert np.allclose(P[k] - p[k], -1e-2 * np.sign(g[k]), rtol=1e-12, atol=1e-15)
+
+
+def test_window_fit_boundary_cases():
+    """f[31] where its boundary decides: 256-row tiles, n = 20600 (the last
+    tile holds 120 rows).  Tile 40 (rows 10240..10495) has one entry in
+    column 256: window 10496 - 256 = 10240 rows = exactly 160 KiB at 16
+    bytes a row, so it fits.  Tile 60 (rows 15360..15615) has one entry in
+    column 15616 - 10241: window 10241 rows, 16 bytes over, so it does not.
+    The last tile has one entry in column 20600 - 10240: its window, with
+    the tile's end clipped to n, is exactly 160 KiB (unclipped it would not
+    fit).  Every other tile is empty and fits.  So f[31] = 80/81; a row size
+    of 8 bytes would give 81/81, '<' for '<=' 78/81 and an unclipped last
+    tile 79/81."""
+    n = 20600
+    rows = [10300, 15400, 20590]
+    cols = [256, 15616 - 10241, 20600 - 10240]
+    rowptr = np.zeros(n + 1, np.int32)
+    for r in rows:
+        rowptr[r + 1:] += 1
+    L = synth.Lower(n, rowptr, np.array(cols, np.int32), np.ones(3))
+    f = oracle.features(L)
+    assert f[31] == 80 / 81
+
+
+def test_distance_shares_at_their_thresholds():
+    """f[19..21] (shares with d/beta > 1/2, 3/4, 9/10) where d sits exactly at
+    each threshold: beta = 20 and d in {20, 10, 15, 18, 11, 16, 19}, one
+    entry per row.  d = 10, 15 and 18 equal beta/2, 3 beta/4 and 9 beta/10
+    and do not count: 6/7, 4/7 and 2/7 ('>=' would give 7/7, 5/7, 3/7).
+    f[11..18] (d <= 1, 2, 4, ..., 128) are 0, 0, 0, 0, 4/7 and then 1."""
+    n = 40
+    rc = [(30, 10), (31, 21), (32, 17), (33, 15), (34, 23), (35, 19), (36, 17)]
+    rowptr = np.zeros(n + 1, np.int32)
+    for r, _ in rc:
+        rowptr[r + 1:] += 1
+    L = synth.Lower(n, rowptr, np.array([c for _, c in rc], np.int32), np.ones(len(rc)))
+    assert sorted(r - c for r, c in rc) == [10, 11, 15, 16, 18, 19, 20]
+    f = oracle.features(L)
+    assert f[3] == 20 / n and f[4] == np.log2(21)
+    assert list(f[19:22]) == [6 / 7, 4 / 7, 2 / 7]
+    assert list(f[11:19]) == [0.0, 0.0, 0.0, 0.0, 4 / 7, 1.0, 1.0, 1.0]

@@ -102,3 +102,20 @@ def test_singular_alpha_zero_odd_n():
     x, info, _ = oracle.mrs(L, 0.0, b, tol=1e-12, maxit=50)
     assert info["status"] in (1, 2)
     assert info["relres"] > 1e-6
+
+
+def test_exit_residual_is_the_full_csr_definition():
+    """info['relres'] of the oracle's MRS is ||b - A x|| / ||b|| with A x from
+    the full CSR of alpha*I + S (recomputed here by a dense product)."""
+    L = synth.rgg2d(300, 8.0, 5)
+    alpha = 0.3
+    b = synth.vector(L.n, 2)
+    x, info, _ = oracle.mrs(L, alpha, b, tol=1e-6, maxit=40)
+    A = alpha * np.eye(L.n)
+    for i in range(L.n):
+        for e in range(L.rowptr[i], L.rowptr[i + 1]):
+            j = L.col[e]
+            A[i, j] += L.val[e]
+            A[j, i] -= L.val[e]
+    r = b - A @ x
+    assert abs(info["relres"] - np.linalg.norm(r) / np.linalg.norm(b)) <= 1e-12 * info["relres"] + 1e-300

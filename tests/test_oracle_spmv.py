@@ -97,3 +97,13 @@ def test_full_csr_layout():
         assert np.all(np.diff(c) > 0)
     frow_a, fcol_a, _ = oracle.full_csr(L, 1.5)
     assert frow_a[-1] == 2 * L.nnz + L.n
+
+
+def test_parallel_full_csr_product_equals_serial():
+    """The all-core baseline shares rows among threads; each row is summed
+    alone in the same order, so the result is the serial one bit for bit."""
+    L = synth.grid3d(30, 4, "normal")
+    frow, fcol, fval = oracle.full_csr(L, 0.5)
+    x = synth.vector(L.n, 9)
+    assert np.array_equal(oracle.csr_spmv_par(frow, fcol, fval, x), oracle.csr_spmv(frow, fcol, fval, x))
+    assert oracle.num_threads() >= 1
