@@ -174,12 +174,34 @@ pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *p, void *s
  * numbering; PARS3_ORDER_ORIGINAL: in the caller's numbering (a gather and a
  * scatter are added).  x and y must not overlap and, when k > 1, must be
  * 16-byte aligned (rows are read and written as 16-byte vectors).
- * Asynchronous.  Errors:
- * Neither allocates nor waits for the stream, so it may be captured in a
- * hipGraph (in both orders).  Errors:
- * ESTATE before pars3_reorder or for a dtype mismatch; EINVAL otherwise. */
+ * Asynchronous: neither allocates nor waits for the stream, so it may be
+ * captured in a hipGraph (in both orders).  Errors: ESTATE before
+ * pars3_reorder or for a dtype mismatch; EINVAL otherwise. */
 pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x, void *y, int32_t k, int32_t vec_dtype,
                         int32_t order, void *stream);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the product
+ * of pars3_spmv with PARS3_ORDER_ORIGINAL (x and y in the caller's numbering,
+ * same arguments and kernels, so the same results up to the order in which
+ * the product adds its per-row sums, which may vary from call to call in
+ * either entry point), whose reordered
+ * copies of x and y live in a fixed device array of the library
+ * (PARS3_NOALLOC_SCRATCH_BYTES = 64 MiB per GPU, reserved when the library's
+ * code is loaded on that GPU and held until the process ends) instead of the
+ * handle's scratch.  Limit: n x k x (8 for FP64, 4 for FP32) <= 32 MiB, half
+ * of the array per vector (e.g. n <= 4,194,304 rows for one FP64 right-hand
+ * side); larger inputs return EINVAL.  Calls no hipMalloc, hipFree or other
+ * allocating routine; the array's device address is looked up once per GPU
+ * on the first call there.  Every call on one GPU uses the same array and
+ * leaves its contents behind; each call writes every byte it reads first, so
+ * nothing needs clearing.  Calls that overlap in time on one GPU (several
+ * streams, or host threads) race on the array and give wrong results: order
+ * them on one stream.  Asynchronous.  Errors as pars3_spmv, plus ESTATE while
+ * per-kernel timing is on (pars3_set_profiling records events). */
+#define PARS3_NOALLOC_SCRATCH_BYTES (64ll << 20)
+pars3_status pars3_spmv_noalloc(pars3_matrix *A, double shift, const void *x, void *y, int32_t k,
+                                int32_t vec_dtype, void *stream);
 
 /* Inspection (host output buffers, caller-allocated; synchronous).
  * perm[n]: new position k holds old node perm[k].  The permuted strictly lower

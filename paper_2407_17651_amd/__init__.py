@@ -103,6 +103,7 @@ SIGNATURES = {
     "pars3_destroy": ([_vp], None),
     "pars3_reorder": ([_vp, ctypes.POINTER(SplitParams), _vp], _st),
     "pars3_spmv": ([_vp, _d, _vp, _vp, _i32, _i32, _i32, _vp], _st),
+    "pars3_spmv_noalloc": ([_vp, _d, _vp, _vp, _i32, _i32, _vp], _st),
     "pars3_get_perm": ([_vp, _vp], _st),
     "pars3_get_permuted_lower": ([_vp, _vp, _vp, _vp, _vp], _st),
     "pars3_get_split_info": ([_vp, ctypes.POINTER(SplitInfo)], _st),
@@ -274,6 +275,11 @@ def pars3_reorder(h, params: SplitParams | None = None, stream=None):
 def pars3_spmv(h, shift, x, y, k=1, vec_dtype=F64, order=ORDER_RCM, stream=None):
     _check(lib().pars3_spmv(h, float(shift), _ptr(x), _ptr(y), int(k), int(vec_dtype), int(order), _stream(stream)),
            "pars3_spmv")
+
+
+def pars3_spmv_noalloc(h, shift, x, y, k=1, vec_dtype=F64, stream=None):
+    _check(lib().pars3_spmv_noalloc(h, float(shift), _ptr(x), _ptr(y), int(k), int(vec_dtype), _stream(stream)),
+           "pars3_spmv_noalloc")
 
 
 def pars3_get_perm(h, n) -> np.ndarray:

@@ -2,6 +2,7 @@
 // inspection.  Argument checks run on the host before any device work.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.h"
@@ -216,6 +217,71 @@ extern "C" pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x,
   P3_TRY(p3::prof_mark(A, p3::PROF_FIXUP, 0, s));
   P3_TRY(p3::scatter_rows(A->yr.p, y, A->perm.p, A->n, k, elem, s));
   P3_TRY(p3::prof_mark(A, p3::PROF_FIXUP, 1, s));
+  return PARS3_OK;
+}
+
+// ------------------------------------------------------------ allocation-free caller-order product
+// Scratch of pars3_spmv_noalloc: x and y in the reordered numbering, one half
+// each, in a file-scope device array (every GPU the library runs on holds its
+// own copy until the process ends).  Host code never passes the array's name
+// to a kernel or a copy (on the host it only stands in for the symbol): the
+// device address of each GPU's copy is looked up once per device, with that
+// device current, and kept in noalloc_ptr.
+static constexpr size_t NOALLOC_BYTES = (size_t)PARS3_NOALLOC_SCRATCH_BYTES;
+static constexpr size_t NOALLOC_HALF = NOALLOC_BYTES / 2;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex noalloc_mu;
+static char *noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+static pars3_status noalloc_scratch(int dev, char **out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(PARS3_EINVAL, "spmv_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> g(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    int cur = 0;
+    P3_HIP(hipGetDevice(&cur));
+    if (cur != dev) P3_HIP(hipSetDevice(dev));
+    void *q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !q) {
+      (void)hipGetLastError();
+      return fail(PARS3_EHIP, "spmv_noalloc: hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    }
+    noalloc_ptr[dev] = (char *)q;
+  }
+  *out = noalloc_ptr[dev];
+  return PARS3_OK;
+}
+
+extern "C" pars3_status pars3_spmv_noalloc(pars3_matrix *A, double shift, const void *x, void *y, int32_t k,
+                                           int32_t vec_dtype, void *stream) {
+  if (!A) return fail(PARS3_EINVAL, "spmv_noalloc: NULL handle");
+  if (!A->split_done) return fail(PARS3_ESTATE, "spmv_noalloc: call pars3_reorder first");
+  if (k != 1 && k != 2 && k != 4 && k != 8) return fail(PARS3_EINVAL, "spmv_noalloc: k must be 1, 2, 4 or 8");
+  if (vec_dtype != PARS3_F64 && vec_dtype != PARS3_F32) return fail(PARS3_EINVAL, "spmv_noalloc: bad vec_dtype");
+  if (k > 1 && (((uintptr_t)x | (uintptr_t)y) & 15u))
+    return fail(PARS3_EINVAL, "spmv_noalloc: x and y must be 16-byte aligned when k > 1");
+  // per-kernel timing records events, which may allocate
+  if (A->prof.on) return fail(PARS3_ESTATE, "spmv_noalloc: switch profiling off (pars3_set_profiling)");
+  const size_t elem = vec_dtype == PARS3_F64 ? 8 : 4;
+  const size_t bytes = (size_t)A->n * k * elem;
+  if (bytes > NOALLOC_HALF)
+    return fail(PARS3_EINVAL, "spmv_noalloc: n x k x %zu = %zu bytes per vector exceeds the %zu-byte limit", elem,
+                bytes, NOALLOC_HALF);
+  if (A->n == 0) return PARS3_OK;
+  if (!x || !y) return fail(PARS3_EINVAL, "spmv_noalloc: NULL vector");
+  if (overlap(x, y, bytes)) return fail(PARS3_EINVAL, "spmv_noalloc: x and y overlap");
+  char *base = nullptr;
+  P3_TRY(noalloc_scratch(A->device, &base));
+  // every byte of both halves that the product reads is written first in
+  // this call (the gather fills x, the product every row of y), so nothing
+  // of an earlier call's contents needs clearing
+  hipStream_t s = (hipStream_t)stream;
+  P3_TRY(p3::gather_rows(x, base, A->perm.p, A->n, k, elem, s));
+  P3_TRY(p3::spmv_rcm(A, shift, base, base + NOALLOC_HALF, k, vec_dtype, s));
+  P3_TRY(p3::scatter_rows(base + NOALLOC_HALF, y, A->perm.p, A->n, k, elem, s));
   return PARS3_OK;
 }
 
