@@ -76,7 +76,19 @@ typedef struct {
   int32_t value_dtype; /* pars3_dtype of the stored values used by pars3_spmv */
   int32_t keep_fp64;   /* also keep FP64 values (needed by the mixed-precision solver) */
   int32_t permute;     /* 1 = reverse Cuthill-McKee (default); 0 = keep the given order */
+  int32_t engine;      /* pars3_engine of pars3_spmv's one-right-hand-side products */
 } pars3_split_params;
+
+/* Which kernel serves pars3_spmv (and pars3_spmv_noalloc) with one
+ * right-hand side.  PARS3_ENGINE_TILES: the skew product over the split
+ * (the method).  PARS3_ENGINE_CSR: pars3_reorder also builds the full CSR of
+ * the reordered matrix (both triangles; rocSPARSE, as pars3_csr_create with
+ * the stored FP64 or FP32 values) and those products run on it, for matrices
+ * where the split does not pay (power-law degree distributions, whose
+ * reordered bandwidth stays near n); the learned selector can choose it.
+ * Products with several right-hand sides, the solvers and batches always use
+ * the split.  Not with BF16 values (EINVAL). */
+typedef enum { PARS3_ENGINE_TILES = 0, PARS3_ENGINE_CSR = 1 } pars3_engine;
 
 /* Fills `p` with the defaults (RCM, paper split, 256-row tiles, FP64). */
 void pars3_split_params_default(pars3_split_params *p);
@@ -93,6 +105,7 @@ typedef struct {
   int32_t max_blocks;        /* max over tiles of blocks read on one side */
   int32_t n_components;      /* connected components of the graph of S */
   int32_t bfs_levels;        /* levels of the Cuthill-McKee search (max over components) */
+  int32_t engine;            /* pars3_engine in use */
 } pars3_split_info;
 
 /* Host-only validation of a strictly lower CSR (no device use).  Checks, rows
@@ -173,7 +186,10 @@ pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params *p, void *s
  * formed in FP32, summed per row in FP64, results rounded to FP32).  order = PARS3_ORDER_RCM: x and y are in the reordered
  * numbering; PARS3_ORDER_ORIGINAL: in the caller's numbering (a gather and a
  * scatter are added).  x and y must not overlap and, when k > 1, must be
- * 16-byte aligned (rows are read and written as 16-byte vectors).
+ * 16-byte aligned (rows are read and written as 16-byte vectors).  On a
+ * handle reordered with engine = PARS3_ENGINE_CSR, products with k = 1 in the
+ * values' precision run on its full CSR (rocSPARSE; with shift != 0 a
+ * scaled copy of x into y first).
  * Asynchronous: neither allocates nor waits for the stream, so it may be
  * captured in a hipGraph (in both orders).  Errors: ESTATE before
  * pars3_reorder or for a dtype mismatch; EINVAL otherwise. */
@@ -189,7 +205,8 @@ pars3_status pars3_spmv(pars3_matrix *A, double shift, const void *x, void *y, i
  * copies of x and y live in a fixed device array of the library
  * (PARS3_NOALLOC_SCRATCH_BYTES = 64 MiB per GPU, reserved when the library's
  * code is loaded on that GPU and held until the process ends) instead of the
- * handle's scratch.  Limit: n x k x (8 for FP64, 4 for FP32) <= 32 MiB, half
+ * handle's scratch, and always on the split's kernel (also on a handle with
+ * engine = PARS3_ENGINE_CSR).  Limit: n x k x (8 for FP64, 4 for FP32) <= 32 MiB, half
  * of the array per vector (e.g. n <= 4,194,304 rows for one FP64 right-hand
  * side); larger inputs return EINVAL.  Calls no hipMalloc, hipFree or other
  * allocating routine; the array's device address is looked up once per GPU
@@ -257,6 +274,21 @@ typedef struct {
 pars3_status pars3_conflict_map(const pars3_matrix *A, int32_t nblocks, const int64_t *bounds,
                                 pars3_block_conflicts *out, void *stream);
 
+/* Three features of the conflict map over nblocks balanced row blocks of the
+ * reordered matrix (Section 3, Fig. 2; the closing remarks of Section 4.1
+ * propose identifying the data races ahead of time for a given number of
+ * processors), the learned selector's inputs 33-35 with nblocks =
+ * PARS3_SELECT_BLOCKS, the 8 XCDs whose contiguous tile ranges the product
+ * spreads its work over:
+ *   feat3[0] = conflicting (R2) entries of all blocks / nnz (0 when nnz = 0)
+ *   feat3[1] = max over blocks of halo / rows
+ *   feat3[2] = max over blocks of (first_row - reach) / rows
+ * (rows of an empty block count as 1).  Ratios of integer counts, so
+ * bit-exact against the same definition on the host.  Synchronous.  Errors
+ * as pars3_conflict_map. */
+#define PARS3_SELECT_BLOCKS 8
+pars3_status pars3_conflict_features(const pars3_matrix *A, int32_t nblocks, double *feat3, void *stream);
+
 /* Full-CSR comparison path (the storage that keeps every nonzero, Section 1).
  * pars3_csr_create builds, on the GPU, the full CSR of S (both triangles,
  * 2*nnz entries, columns ascending in every row; with a diagonal array, D + S
@@ -283,7 +315,9 @@ void pars3_csr_destroy(pars3_csr *C);
  * height).  pars3_tune_grid_default writes the default grid for one value
  * precision into grid[0..cap) and its size into *count (grid may be NULL to
  * query the size): tile_rows in {64, 128, 256, 512, 1024} x w_in in {0, 1, 2, 4} x
- * t_out in {paper (-1: beta - 3), -2: half the RCM bandwidth}.
+ * t_out in {paper (-1: beta - 3), -2: half the RCM bandwidth} (40 entries),
+ * then, for FP64 and FP32 values, one entry with engine = PARS3_ENGINE_CSR
+ * (the full-CSR product; 41 entries).
  * pars3_autotune applies every configuration of grid[0..ngrid) to A (the
  * reordering is computed once and kept; t_out = -1 and -2 are resolved against
  * beta, and t_out is raised to w_in where it would fall below it), times
@@ -496,8 +530,10 @@ pars3_status pars3_mlp_set_grid(pars3_mlp *m, const pars3_split_params *grid, in
 pars3_status pars3_mlp_get_grid(const pars3_mlp *m, pars3_split_params *grid, int32_t cap, int32_t *count);
 
 /* Trained selector on disk (a binary file, little-endian): the magic
- * "PARS3MLP", format version 1 (uint32), int32 n_in, h1, h2, n_out, ngrid,
- * ngrid x 6 int32 split parameters in pars3_split_params field order, the
+ * "PARS3MLP", format version 2 (uint32), int32 n_in, h1, h2, n_out, ngrid,
+ * ngrid x 7 int32 split parameters in pars3_split_params field order
+ * (version 1 files, which hold the first 6 and no engine, load with engine
+ * PARS3_ENGINE_TILES), the
  * scaler (n_in float means, n_in float standard deviations), the packed
  * weights (float, as pars3_mlp_get_params) and a 64-bit FNV-1a hash of every
  * preceding byte.  save: needs a grid (ESTATE otherwise); EIO when the file

@@ -67,6 +67,7 @@ def _L():
             "or_mrs": ([i32, _vp, _vp, _vp, d, _vp, _vp, d, i32, _vp, _vp], ctypes.c_int),
             "or_features": ([i32, _vp, _vp, _vp], ctypes.c_int),
             "or_conflict_map": ([i32, _vp, _vp, _vp, i32, _vp, _vp], ctypes.c_int),
+            "or_conflict_features": ([i32, _vp, _vp, i32, _vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -333,3 +334,17 @@ def conflict_map(L, part, nblocks: int, bounds=None) -> np.ndarray:
     if r != 0:
         raise MemoryError("or_conflict_map")
     return out[:nblocks]
+
+
+def conflict_features(L, nblocks: int = 8) -> np.ndarray:
+    """The 3 conflict features of L over nblocks balanced row blocks (R2
+    share of the entries, largest halo per block row, largest reach per
+    block row; Section 3, Fig. 2), in the numbering L is given in."""
+    n, rp, c, _ = _arrs(L)
+    f = np.zeros(3, np.float64)
+    r = _L().or_conflict_features(n, _p(rp), _p(c), int(nblocks), f.ctypes.data)
+    if r == 1:
+        raise ValueError("bad block count")
+    if r != 0:
+        raise MemoryError("or_conflict_features")
+    return f

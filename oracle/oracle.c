@@ -722,3 +722,43 @@ int or_conflict_map(int32_t n, const int32_t *rowptr, const int32_t *col, const 
   free(R); free(owner); free(seen_col); free(seen_blk);
   return 0;
 }
+
+/* Conflict features of a block-row distribution over nb balanced blocks
+ * (Section 3, Fig. 2: the R2 entries whose column lies in an earlier block;
+ * the closing remarks of Section 4.1 propose finding such races ahead of time
+ * for a given number of processors).  From the conflict map (part only
+ * splits the counts, so none is needed here):
+ *   f[0] = (R2 entries of all blocks) / nnz            (0 when nnz = 0)
+ *   f[1] = max over blocks of halo / rows               (rows >= 1 counted)
+ *   f[2] = max over blocks of (first_row - reach) / rows
+ * Each is a ratio of integers in IEEE double division.  Returns 0, 1 for a
+ * bad block count, -1 when out of memory. */
+int or_conflict_features(int32_t n, const int32_t *rowptr, const int32_t *col, int32_t nb, double *f) {
+  f[0] = f[1] = f[2] = 0.0;
+  if (nb < 1) return 1;
+  const int64_t nnz = rowptr[n];
+  int8_t *part = (int8_t *)calloc((size_t)nnz + 1, 1);
+  int64_t *map = (int64_t *)malloc((size_t)nb * 11 * sizeof(int64_t));
+  if (!part || !map) {
+    free(part); free(map);
+    return -1;
+  }
+  const int r = or_conflict_map(n, rowptr, col, part, nb, NULL, map);
+  if (r != 0) {
+    free(part); free(map);
+    return r;
+  }
+  int64_t conf = 0;
+  for (int32_t p = 0; p < nb; p++) {
+    const int64_t *o = map + (size_t)11 * p;
+    conf += o[5] + o[6] + o[7];
+    const int64_t rows = o[1] > 0 ? o[1] : 1;
+    const double halo = (double)o[10] / (double)rows;
+    const double reach = (double)(o[0] - o[8]) / (double)rows;
+    if (halo > f[1]) f[1] = halo;
+    if (reach > f[2]) f[2] = reach;
+  }
+  f[0] = nnz > 0 ? (double)conf / (double)nnz : 0.0;
+  free(part); free(map);
+  return 0;
+}

@@ -27,6 +27,7 @@ STATUS_NAMES = ["OK", "EINVAL", "ENOTLOWER", "EUNSORTED", "ENOMEM", "EHIP", "EST
 F64, F32, BF16 = 0, 1, 2
 ORDER_RCM, ORDER_ORIGINAL = 0, 1
 SKEW, SYMMETRIC = 0, 1
+ENGINE_TILES, ENGINE_CSR = 0, 1
 
 
 class Pars3Unavailable(RuntimeError):
@@ -41,7 +42,8 @@ class Pars3Error(RuntimeError):
 
 
 class SplitParams(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int32) for f in ("w_in", "t_out", "tile_rows", "value_dtype", "keep_fp64", "permute")]
+    _fields_ = [(f, ctypes.c_int32) for f in ("w_in", "t_out", "tile_rows", "value_dtype", "keep_fp64", "permute",
+                                              "engine")]
 
 
 class SplitInfo(ctypes.Structure):
@@ -51,7 +53,7 @@ class SplitInfo(ctypes.Structure):
         ("tile_rows", ctypes.c_int32), ("value_dtype", ctypes.c_int32), ("permute", ctypes.c_int32),
         ("nnz_inner", ctypes.c_int64), ("nnz_middle", ctypes.c_int64), ("nnz_outer", ctypes.c_int64),
         ("n_tiles", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
-        ("n_components", ctypes.c_int32), ("bfs_levels", ctypes.c_int32),
+        ("n_components", ctypes.c_int32), ("bfs_levels", ctypes.c_int32), ("engine", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -115,6 +117,7 @@ SIGNATURES = {
     "pars3_csr_get": ([_vp, _vp, _vp, _vp], _st),
     "pars3_csr_size": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _st),
     "pars3_conflict_map": ([_vp, _i32, _vp, ctypes.POINTER(BlockConflicts), _vp], _st),
+    "pars3_conflict_features": ([_vp, _i32, _vp, _vp], _st),
     "pars3_csr_destroy": ([_vp], None),
     "pars3_features": ([_vp, _vp, _vp], _st),
     "pars3_tune_grid_default": ([_i32, _vp, _i32, ctypes.POINTER(_i32)], _st),
@@ -184,12 +187,17 @@ def _check(status: int, where: str):
 
 
 def _ptr(a):
-    """Host numpy array or device torch tensor -> address (None for empty)."""
+    """Host numpy array or device torch tensor -> address (None for empty).
+    The library reads row-major contiguous data: anything else is refused."""
     if a is None:
         return None
     if isinstance(a, np.ndarray):
+        if a.size and not a.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous (row-major)")
         return a.ctypes.data if a.size else None
     if hasattr(a, "data_ptr"):
+        if a.numel() and not a.is_contiguous():
+            raise ValueError("tensor must be contiguous (row-major)")
         return a.data_ptr() if a.numel() else None
     return int(a)
 
@@ -344,6 +352,16 @@ def pars3_conflict_map(h, nblocks, bounds=None, stream=None) -> np.ndarray:
     return np.frombuffer(out, np.int64).reshape(-1, 11)[:nb].copy()  # 11 packed int64 per block
 
 
+SELECT_BLOCKS = 8  # PARS3_SELECT_BLOCKS
+
+
+def pars3_conflict_features(h, nblocks=SELECT_BLOCKS, stream=None) -> np.ndarray:
+    """The 3 conflict features over nblocks balanced row blocks (float64[3])."""
+    out = np.zeros(3, np.float64)
+    _check(lib().pars3_conflict_features(h, int(nblocks), _ptr(out), _stream(stream)), "pars3_conflict_features")
+    return out
+
+
 def pars3_csr_size(c):
     n, m = _i64(), _i64()
     _check(lib().pars3_csr_size(c, ctypes.byref(n), ctypes.byref(m)), "pars3_csr_size")
@@ -376,7 +394,7 @@ def pars3_tune_grid_default(value_dtype=F64):
 
 def pars3_autotune(h, grid=None, k=1, reps=20, stream=None, value_dtype=F64):
     """Returns (results, best): results is a list of dicts {w_in, t_out,
-    tile_rows, value_dtype, us}."""
+    tile_rows, value_dtype, engine, us}."""
     if grid is None:
         grid = pars3_tune_grid_default(value_dtype)
     out = (TuneResult * len(grid))()
@@ -384,7 +402,7 @@ def pars3_autotune(h, grid=None, k=1, reps=20, stream=None, value_dtype=F64):
     _check(lib().pars3_autotune(h, grid, len(grid), int(k), int(reps), out, ctypes.byref(best), _stream(stream)),
            "pars3_autotune")
     res = [{"w_in": r.params.w_in, "t_out": r.params.t_out, "tile_rows": r.params.tile_rows,
-            "value_dtype": r.params.value_dtype, "us": r.us} for r in out]
+            "value_dtype": r.params.value_dtype, "engine": r.params.engine, "us": r.us} for r in out]
     return res, best.value
 
 
@@ -679,6 +697,9 @@ class Matrix:
 
     def conflict_map(self, nblocks, bounds=None):
         return pars3_conflict_map(self.h, nblocks, bounds)
+
+    def conflict_features(self, nblocks=SELECT_BLOCKS):
+        return pars3_conflict_features(self.h, nblocks)
 
     def diagonal(self):
         """The diagonal array in the reordered numbering."""

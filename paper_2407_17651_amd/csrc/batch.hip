@@ -101,6 +101,10 @@ __global__ void k_bmrs_init(bmrs_ptrs p, const double *__restrict__ bn2, const d
   d.done = (beta1 == 0.0 || beta1 <= d.tol_abs || maxit <= 0) ? 1 : 0;
   d.active = 0;
   d.status = 0;
+  if (!isfinite(beta1) || !isfinite(bnorm)) {  // a NaN or Inf in b, x0 or the matrix
+    d.done = 1;
+    d.status = 3;
+  }
 }
 
 // W_0 = v_1 = -y / ||y|| (unnormalised Lanczos vectors W_k live in

@@ -188,3 +188,23 @@ extern "C" pars3_status pars3_conflict_map(const pars3_matrix *A, int32_t nblock
   }
   return PARS3_OK;
 }
+
+extern "C" pars3_status pars3_conflict_features(const pars3_matrix *A, int32_t nblocks, double *feat3, void *stream) {
+  using namespace p3;
+  if (!A || !feat3) return fail(PARS3_EINVAL, "conflict_features: NULL argument");
+  if (nblocks < 1) return fail(PARS3_EINVAL, "conflict_features: nblocks must be >= 1");
+  std::vector<pars3_block_conflicts> blk((size_t)nblocks);
+  P3_TRY(pars3_conflict_map(A, nblocks, nullptr, blk.data(), stream));
+  int64_t conf = 0;
+  double halo = 0.0, reach = 0.0;
+  for (const pars3_block_conflicts &o : blk) {
+    conf += o.conflict[0] + o.conflict[1] + o.conflict[2];
+    const int64_t rows = o.rows > 0 ? o.rows : 1;
+    halo = std::max(halo, (double)o.halo / (double)rows);
+    reach = std::max(reach, (double)(o.first_row - o.reach) / (double)rows);
+  }
+  feat3[0] = A->nnz > 0 ? (double)conf / (double)A->nnz : 0.0;
+  feat3[1] = halo;
+  feat3[2] = reach;
+  return PARS3_OK;
+}

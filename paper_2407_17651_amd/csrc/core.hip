@@ -17,6 +17,7 @@ extern "C" void pars3_split_params_default(pars3_split_params *p) {
   p->value_dtype = PARS3_F64;
   p->keep_fp64 = 0;
   p->permute = 1;
+  p->engine = PARS3_ENGINE_TILES;
 }
 
 extern "C" pars3_status pars3_validate(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col) {
@@ -103,6 +104,7 @@ extern "C" pars3_status pars3_get_diagonal(const pars3_matrix *A, double *out) {
 }
 
 pars3_matrix::~pars3_matrix() {
+  pars3_csr_destroy(csr);
   p3::skew_shadow_free(shadow);
   p3::mrs_ws_free(mrs);
   if (solver_stream) (void)hipStreamDestroy(solver_stream);
@@ -145,6 +147,10 @@ static pars3_status check_params(const pars3_split_params &p) {
   if (p.w_in < -1 || p.t_out < -1) return fail(PARS3_EINVAL, "reorder: w_in and t_out must be >= -1");
   if (p.permute != 0 && p.permute != 1) return fail(PARS3_EINVAL, "reorder: permute must be 0 or 1");
   if (p.keep_fp64 != 0 && p.keep_fp64 != 1) return fail(PARS3_EINVAL, "reorder: keep_fp64 must be 0 or 1");
+  if (p.engine != PARS3_ENGINE_TILES && p.engine != PARS3_ENGINE_CSR)
+    return fail(PARS3_EINVAL, "reorder: engine must be PARS3_ENGINE_TILES or PARS3_ENGINE_CSR");
+  if (p.engine == PARS3_ENGINE_CSR && p.value_dtype == PARS3_BF16)
+    return fail(PARS3_EINVAL, "reorder: the full-CSR engine takes FP64 or FP32 values");
   return PARS3_OK;
 }
 
@@ -173,6 +179,8 @@ extern "C" pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params 
   A->split_done = false;
   p3::skew_shadow_free(A->shadow);  // built for the previous split
   A->shadow = nullptr;
+  pars3_csr_destroy(A->csr);  // built for the previous split
+  A->csr = nullptr;
   P3_TRY(p3::split_and_layout(A, p, s));
   // scratch of products in the caller's numbering (up to 8 FP64 right-hand
   // sides), reserved here so that pars3_spmv never allocates
@@ -184,6 +192,17 @@ extern "C" pars3_status pars3_reorder(pars3_matrix *A, const pars3_split_params 
   }
   P3_HIP(hipStreamSynchronize(s));
   A->split_done = true;
+  if (p.engine == PARS3_ENGINE_CSR && A->n > 0) {
+    // the full CSR of the reordered matrix serves the one-right-hand-side
+    // products; the split stays for everything else
+    pars3_csr *C = nullptr;
+    const pars3_status st = pars3_csr_create(A, PARS3_ORDER_RCM, A->lay.vdtype, &C);
+    if (st != PARS3_OK) {
+      A->split_done = false;
+      return st;
+    }
+    A->csr = C;
+  }
   return PARS3_OK;
 }
 
@@ -280,7 +299,8 @@ extern "C" pars3_status pars3_spmv_noalloc(pars3_matrix *A, double shift, const 
   // of an earlier call's contents needs clearing
   hipStream_t s = (hipStream_t)stream;
   P3_TRY(p3::gather_rows(x, base, A->perm.p, A->n, k, elem, s));
-  P3_TRY(p3::spmv_rcm(A, shift, base, base + NOALLOC_HALF, k, vec_dtype, s));
+  // always the split's kernel (the full-CSR engine's library calls may allocate)
+  P3_TRY(p3::spmv_ex(A, shift, base, base + NOALLOC_HALF, k, vec_dtype, -1, s, nullptr));
   P3_TRY(p3::scatter_rows(base + NOALLOC_HALF, y, A->perm.p, A->n, k, elem, s));
   return PARS3_OK;
 }
@@ -319,6 +339,7 @@ extern "C" pars3_status pars3_get_split_info(const pars3_matrix *A, pars3_split_
   info->tile_rows = L.T;
   info->value_dtype = L.vdtype;
   info->permute = A->perm_kind;
+  info->engine = A->csr ? PARS3_ENGINE_CSR : PARS3_ENGINE_TILES;
   info->nnz_inner = A->cnt[0];
   info->nnz_middle = A->cnt[1];
   info->nnz_outer = A->cnt[2];

@@ -296,6 +296,48 @@ extern "C" pars3_status pars3_csr_spmv(pars3_csr *C, double shift, const void *x
   return PARS3_OK;
 }
 
+namespace p3 {
+template <class X>
+__global__ void k_scale_copy(const X *__restrict__ x, X *__restrict__ y, X a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+// y = shift x + S x with rocSPARSE (the engine of a handle reordered with
+// PARS3_ENGINE_CSR): y = shift x first, then y = S x + y (beta = 1); with
+// shift = 0 the product alone (beta = 0).
+pars3_status csr_product(pars3_csr *C, double shift, const void *x, void *y, hipStream_t s) {
+  if (C->n == 0) return PARS3_OK;
+  if (!C->rs_ready) return fail(PARS3_ESTATE, "spmv: the full CSR was not prepared");
+  const bool f64 = C->vdtype == PARS3_F64;
+  if (shift != 0.0) {
+    if (f64) k_scale_copy<double><<<nblk(C->n), TB, 0, s>>>((const double *)x, (double *)y, shift, C->n);
+    else k_scale_copy<float><<<nblk(C->n), TB, 0, s>>>((const float *)x, (float *)y, (float)shift, C->n);
+    P3_LAUNCHED();
+  }
+  P3_RS(rocsparse_set_stream(C->rh, s));
+  const rocsparse_datatype dt = f64 ? rocsparse_datatype_f64_r : rocsparse_datatype_f32_r;
+  rocsparse_dnvec_descr dx = nullptr, dy = nullptr;
+  P3_RS(rocsparse_create_dnvec_descr(&dx, C->n, const_cast<void *>(x), dt));
+  const rocsparse_status ry = rocsparse_create_dnvec_descr(&dy, C->n, y, dt);
+  if (ry != rocsparse_status_success) {
+    rocsparse_destroy_dnvec_descr(dx);
+    return fail(PARS3_EHIP, "spmv: rocsparse_create_dnvec_descr failed (%d)", (int)ry);
+  }
+  const double one64 = 1.0, b64 = shift != 0.0 ? 1.0 : 0.0;
+  const float one32 = 1.f, b32 = shift != 0.0 ? 1.f : 0.f;
+  const rocsparse_status r =
+      rocsparse_spmv(C->rh, rocsparse_operation_none, f64 ? (const void *)&one64 : (const void *)&one32, C->mat, dx,
+                     f64 ? (const void *)&b64 : (const void *)&b32, dy, dt, rocsparse_spmv_alg_default,
+                     rocsparse_spmv_stage_compute, &C->bufsz, C->buf.p);
+  rocsparse_destroy_dnvec_descr(dx);
+  rocsparse_destroy_dnvec_descr(dy);
+  if (r != rocsparse_status_success) return fail(PARS3_EHIP, "spmv: rocsparse_spmv failed (%d)", (int)r);
+  return PARS3_OK;
+}
+int32_t csr_vdtype(const pars3_csr *C) { return C->vdtype; }
+}  // namespace p3
+
 extern "C" pars3_status pars3_csr_size(const pars3_csr *C, int64_t *n, int64_t *nnz_full) {
   if (!C) return fail(PARS3_EINVAL, "csr_size: NULL handle");
   if (n) *n = C->n;

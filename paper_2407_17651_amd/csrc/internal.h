@@ -235,6 +235,8 @@ struct pars3_matrix {
   // numbering, n rows of up to ORIG_MAX_ROW_BYTES each, reserved by
   // pars3_reorder so that pars3_spmv never allocates or synchronises
   p3::dbuf<char> xr, yr;
+  // full CSR serving one-right-hand-side products (engine PARS3_ENGINE_CSR)
+  pars3_csr *csr = nullptr;
   // solver stream and workspace (mrs.hip), created on first use
   hipStream_t solver_stream = nullptr;
   p3::mrs_ws *mrs = nullptr;
@@ -387,6 +389,10 @@ pars3_status launch_batch(int vkind, int k, bool ep, bool gen, const prod_task *
 // skewform.hip: MRS for alpha*I + D + S through its shifted skew form
 pars3_status mrs_shifted(pars3_matrix *A, double alpha, const double *b, double *x, const pars3_mrs_opts &o,
                          pars3_mrs_info *info, hipStream_t s);
+// csr.hip: y = shift x + S x on a handle's full CSR (rocSPARSE), and the
+// precision of its values
+pars3_status csr_product(pars3_csr *C, double shift, const void *x, void *y, hipStream_t s);
+int32_t csr_vdtype(const pars3_csr *C);
 // A symmetric matrix or one with a diagonal array (the general kernels).
 inline bool is_general(const pars3_matrix *A) { return A->kind != PARS3_SKEW || A->diag.p != nullptr; }
 // Product with an optional epilogue; value_dtype selects FP32 or BF16 values

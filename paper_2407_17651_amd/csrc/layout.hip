@@ -14,7 +14,9 @@
 // are all distinct, so the 64 lanes of a chunk mostly add into 64 different
 // LDS rows on both the row side and the column side (lanes adding into one
 // address are serialised).
-// Each entry stores ((i - t*T) << 16 | (j - u*T)) and its value.  Per row
+// Each entry stores its value and the word ((i - t*T) << SH | (j - u*T)):
+// 16 bits with SH = 8 for tiles of at most 256 rows, 32 bits with SH = 16
+// for taller ones.  Per row
 // tile: its block range; per column tile: the list of blocks whose column tile
 // it is.  The product reads, per tile, its own blocks (row side) and the
 // blocks of its column list (column side), cut into chunks of at most 64

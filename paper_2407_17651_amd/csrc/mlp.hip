@@ -525,16 +525,16 @@ extern "C" pars3_status pars3_mlp_get_grid(const pars3_mlp *m, pars3_split_param
 
 // Model file: little-endian, in this order
 //   char[8]  magic "PARS3MLP"
-//   uint32   format version (1)
+//   uint32   format version (2; version 1 files load too)
 //   int32    n_in, h1, h2, n_out, ngrid (= n_out)
-//   int32    ngrid x 6 split parameters (w_in, t_out, tile_rows, value_dtype,
-//            keep_fp64, permute)
+//   int32    ngrid x 7 split parameters (w_in, t_out, tile_rows, value_dtype,
+//            keep_fp64, permute, engine); version 1: 6 of them, engine 0
 //   float    n_in feature means, n_in feature standard deviations
 //   float    n_params weights packed W1, b1, W2, b2, W3, b3
 //   uint64   FNV-1a hash of every byte above
 namespace {
 constexpr char kMagic[8] = {'P', 'A', 'R', 'S', '3', 'M', 'L', 'P'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct fnv_writer {
   FILE *f;
@@ -575,7 +575,7 @@ extern "C" pars3_status pars3_model_save(const pars3_mlp *m, const char *path) {
   const int32_t hdr[5] = {m->n_in, m->h1, m->h2, m->n_out, (int32_t)m->grid.size()};
   w.put(hdr, sizeof(hdr));
   for (const pars3_split_params &g : m->grid) {
-    const int32_t v[6] = {g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute};
+    const int32_t v[7] = {g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute, g.engine};
     w.put(v, sizeof(v));
   }
   w.put(mean.data(), mean.size() * sizeof(float));
@@ -605,20 +605,22 @@ extern "C" pars3_status pars3_model_load(const char *path, pars3_mlp **out) {
   };
   if (!r.ok) return bad("truncated header");
   if (std::memcmp(magic, kMagic, 8) != 0) return bad("not a model file");
-  if (ver != kVersion) return bad("unknown format version");
+  if (ver != 1 && ver != kVersion) return bad("unknown format version");
   for (int k = 0; k < 4; k++)
     if (hdr[k] < 1 || hdr[k] > 4096) return bad("layer size out of range");
   if (hdr[4] != hdr[3]) return bad("grid size differs from the output count");
   std::vector<pars3_split_params> grid(hdr[4]);
+  const size_t nfield = ver == 1 ? 6 : 7;
   for (auto &g : grid) {
-    int32_t v[6];
-    r.get(v, sizeof(v));
+    int32_t v[7] = {0, 0, 0, 0, 0, 0, PARS3_ENGINE_TILES};
+    r.get(v, nfield * sizeof(int32_t));
     g.w_in = v[0];
     g.t_out = v[1];
     g.tile_rows = v[2];
     g.value_dtype = v[3];
     g.keep_fp64 = v[4];
     g.permute = v[5];
+    g.engine = v[6];
   }
   const int64_t np = (int64_t)hdr[0] * hdr[1] + hdr[1] + (int64_t)hdr[1] * hdr[2] + hdr[2] +
                      (int64_t)hdr[2] * hdr[3] + hdr[3];

@@ -400,13 +400,18 @@ extern "C" pars3_status pars3_mrs_solve(pars3_matrix *A, double alpha, const dou
   if (!mixed) {
     // r0 = b - A x0: y = A x0 - b, v_1 = -y / ||y||
     P3_TRY(residual64(A, alpha, ws.xr.p, ws.br.p, ws.yr.p, ws.partials.p, minus_one, s, &rnorm));
-    if (rnorm > 0.0) {
-      k_neg_scale<double, double><<<nblk(n), TB, 0, s>>>(ws.yr.p, (double *)ws.vb0.p, 1.0 / rnorm, n);
-      P3_LAUNCHED();
+    if (!std::isfinite(rnorm) || !std::isfinite(bnorm)) {
+      // a NaN or Inf in b, x0 or the matrix: nothing to iterate on
+      status = 3;
+    } else {
+      if (rnorm > 0.0) {
+        k_neg_scale<double, double><<<nblk(n), TB, 0, s>>>(ws.yr.p, (double *)ws.vb0.p, 1.0 / rnorm, n);
+        P3_LAUNCHED();
+      }
+      st = mrs_iterate<double>(A, -1, alpha, rnorm, bscale, o.tol * bnorm, o.maxit, o.check_every, ws, ws.xr.p, s,
+                               &iters, &status, &eta, hist_len > 0 ? ws.hist.p : nullptr);
+      if (st != PARS3_OK) return st;
     }
-    st = mrs_iterate<double>(A, -1, alpha, rnorm, bscale, o.tol * bnorm, o.maxit, o.check_every, ws, ws.xr.p, s,
-                             &iters, &status, &eta, hist_len > 0 ? ws.hist.p : nullptr);
-    if (st != PARS3_OK) return st;
   } else {
     const double itol = o.inner_tol > 0.0 ? o.inner_tol : (o.precision == PARS3_F32 ? 1e-6 : 1e-2);
     int32_t budget = o.maxit;

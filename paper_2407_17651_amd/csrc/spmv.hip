@@ -651,6 +651,8 @@ pars3_status spmv_ex(pars3_matrix *A, double shift, const void *x, void *y, int 
 }
 
 pars3_status spmv_rcm(pars3_matrix *A, double shift, const void *x, void *y, int k, int vec_dtype, hipStream_t s) {
+  // engine PARS3_ENGINE_CSR: one right-hand side in the CSR's own precision
+  if (A->csr && k == 1 && vec_dtype == csr_vdtype(A->csr)) return csr_product(A->csr, shift, x, y, s);
   return spmv_ex(A, shift, x, y, k, vec_dtype, -1, s, nullptr);
 }
 

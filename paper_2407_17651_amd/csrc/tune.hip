@@ -47,7 +47,9 @@ extern "C" pars3_status pars3_tune_grid_default(int32_t value_dtype, pars3_split
   if (!count) return fail(PARS3_EINVAL, "tune grid: NULL count");
   if (value_dtype != PARS3_F64 && value_dtype != PARS3_F32 && value_dtype != PARS3_BF16)
     return fail(PARS3_EINVAL, "tune grid: bad value_dtype");
-  const int32_t total = (int32_t)(sizeof(kTiles) / sizeof(kTiles[0]) * sizeof(kWin) / sizeof(kWin[0]) * 2);
+  // every tile configuration, then (FP64 and FP32 values) the full-CSR engine
+  const int32_t tiles = (int32_t)(sizeof(kTiles) / sizeof(kTiles[0]) * sizeof(kWin) / sizeof(kWin[0]) * 2);
+  const int32_t total = tiles + (value_dtype == PARS3_BF16 ? 0 : 1);
   *count = total;
   if (!grid) return PARS3_OK;
   if (cap < total) return fail(PARS3_EINVAL, "tune grid: capacity %d < %d", cap, total);
@@ -64,6 +66,12 @@ extern "C" pars3_status pars3_tune_grid_default(int32_t value_dtype, pars3_split
         p.t_out = half ? -2 : -1;
         p.value_dtype = value_dtype;
       }
+  if (total > tiles) {
+    pars3_split_params &p = grid[q++];
+    pars3_split_params_default(&p);
+    p.value_dtype = value_dtype;
+    p.engine = PARS3_ENGINE_CSR;
+  }
   return PARS3_OK;
 }
 
@@ -80,6 +88,7 @@ extern "C" pars3_status pars3_autotune(pars3_matrix *A, const pars3_split_params
     pars3_split_params p0 = grid[0];
     p0.w_in = 0;
     p0.t_out = -1;
+    p0.engine = PARS3_ENGINE_TILES;
     P3_TRY(pars3_reorder(A, &p0, stream));
   }
   const int32_t beta = A->beta;
@@ -150,8 +159,9 @@ extern "C" pars3_status pars3_select(pars3_matrix *A, pars3_mlp *m, const pars3_
   if (ngrid < 1) return fail(PARS3_EINVAL, "select: empty grid");
   int32_t sz[4];
   P3_TRY(pars3_mlp_sizes(m, sz, nullptr));
-  if (sz[0] != 32 || sz[3] != ngrid)
-    return fail(PARS3_EINVAL, "select: the network maps %d features to %d outputs; need 32 -> %d", sz[0], sz[3], ngrid);
+  if ((sz[0] != 32 && sz[0] != 35) || sz[3] != ngrid)
+    return fail(PARS3_EINVAL, "select: the network maps %d features to %d outputs; need 32 or 35 -> %d", sz[0],
+                sz[3], ngrid);
   hipStream_t s = (hipStream_t)stream;
   // features of the reordered matrix (reorder with the paper's split first
   // when the handle has not been reordered)
@@ -159,17 +169,21 @@ extern "C" pars3_status pars3_select(pars3_matrix *A, pars3_mlp *m, const pars3_
     pars3_split_params p0 = grid[0];
     p0.w_in = 0;
     p0.t_out = -1;
+    p0.engine = PARS3_ENGINE_TILES;
     P3_TRY(pars3_reorder(A, &p0, stream));
   }
-  double f[32];
+  // the 32 features, and for a 35-input network the 3 conflict features
+  // over PARS3_SELECT_BLOCKS row blocks
+  double f[35];
   P3_TRY(pars3_features(A, f, stream));
-  float ff[32];
-  for (int k = 0; k < 32; k++) ff[k] = (float)f[k];
+  if (sz[0] == 35) P3_TRY(pars3_conflict_features(A, PARS3_SELECT_BLOCKS, f + 32, stream));
+  float ff[35];
+  for (int k = 0; k < sz[0]; k++) ff[k] = (float)f[k];
   dbuf<float> xd;
   dbuf<int32_t> cd;
-  P3_HIP(xd.alloc(32));
+  P3_HIP(xd.alloc(sz[0]));
   P3_HIP(cd.alloc(1));
-  P3_HIP(hipMemcpyAsync(xd.p, ff, sizeof(ff), hipMemcpyHostToDevice, s));
+  P3_HIP(hipMemcpyAsync(xd.p, ff, sz[0] * sizeof(float), hipMemcpyHostToDevice, s));
   P3_TRY(pars3_mlp_select_rows(m, xd.p, 1, nullptr, cd.p, stream));
   int32_t c = -1;
   P3_HIP(hipMemcpyAsync(&c, cd.p, sizeof(c), hipMemcpyDeviceToHost, s));
@@ -180,6 +194,7 @@ extern "C" pars3_status pars3_select(pars3_matrix *A, pars3_mlp *m, const pars3_
     pars3_split_params p0 = grid[0];
     p0.w_in = 0;
     p0.t_out = -1;
+    p0.engine = PARS3_ENGINE_TILES;
     P3_TRY(pars3_reorder(A, &p0, stream));
   }
   const pars3_split_params p = resolve(grid[c], A->beta);

@@ -8,11 +8,15 @@ boundary t_out, tile height) and is learned:
 * ``sweep``: for generated matrices (2D/3D stencils, random geometric graphs,
   Chung-Lu power-law graphs; n log-uniform), the exhaustive autotuner
   (``pars3_autotune``) times every configuration of the default grid on the
-  GPU and ``pars3_features`` measures 32 features after reordering.  These
-  records are the training data.
+  GPU (40 tile configurations and the full-CSR engine), ``pars3_features``
+  measures 32 features after reordering and ``pars3_conflict_features`` 3
+  more: the conflicting (R2) share, halo and reach over 8 row blocks (Section
+  3, Fig. 2).  These records are the training data.
+* ``extend``: adds the conflict features and the full-CSR timing to a sweep
+  file made before they existed (the 40 tile timings are kept).
 * ``targets``: T[m, g] = log(t[m, g] / min_g t[m, g]), masked where a
   configuration failed.
-* ``train``: the network (``pars3_mlp``: 32 -> 64 -> 64 -> |G|, ReLU) is
+* ``train``: the network (``pars3_mlp``: 35 -> 64 -> 64 -> |G|, ReLU) is
   fitted with the library's own forward, backward and Adam kernels.
 * ``evaluate``: regret t(selected) / t(best) - 1 on held-out matrices, for
   the network, the paper's configuration (w_in = 0, t_out = beta - 3, 256-row
@@ -20,6 +24,7 @@ boundary t_out, tile height) and is learned:
 
 Command line (GPU):
   python -m paper_2407_17651_amd.selector sweep --start 0 --count 500 --out sweep_0.npz
+  python -m paper_2407_17651_amd.selector extend --start 0 --count 500 --out ext_0.npz
   python -m paper_2407_17651_amd.selector merge OUT IN [IN ...]
   python -m paper_2407_17651_amd.selector evaluate [--data FILE]
 """
@@ -43,16 +48,30 @@ FAMILIES = ("grid2d", "grid3d", "rgg2d", "chung_lu")
 
 
 def grid_table(grid):
-    """(tile_rows, w_in, t_out code) per configuration of a default grid."""
-    return np.array([(g.tile_rows, g.w_in, g.t_out) for g in grid], np.int32)
+    """(tile_rows, w_in, t_out code, engine) per configuration of a default
+    grid."""
+    return np.array([(g.tile_rows, g.w_in, g.t_out, g.engine) for g in grid], np.int32)
 
 
 def paper_config_index(grid) -> int:
     """The paper's split (w_in = 0, outer bandwidth 3) with 256-row tiles."""
     for i, g in enumerate(grid):
-        if g.tile_rows == 256 and g.w_in == 0 and g.t_out == -1:
+        if g.tile_rows == 256 and g.w_in == 0 and g.t_out == -1 and g.engine == 0:
             return i
     raise ValueError("grid lacks the paper configuration")
+
+
+def paper_index(table) -> int:
+    """paper_config_index on a grid_table array."""
+    t = np.asarray(table)
+    eng = t[:, 3] if t.shape[1] > 3 else np.zeros(len(t), np.int32)
+    return int(np.flatnonzero((t[:, 0] == 256) & (t[:, 1] == 0) & (t[:, 2] == -1) & (eng == 0))[0])
+
+
+def features_of(M):
+    """The selector's 35 inputs of a reordered handle: 32 features and 3
+    conflict features over the 8 row blocks."""
+    return np.concatenate([M.features(), M.conflict_features()])
 
 
 def sweep(start: int, count: int, reps: int = 10, value_dtype: int | None = None, log=sys.stdout) -> dict:
@@ -68,13 +87,45 @@ def sweep(start: int, count: int, reps: int = 10, value_dtype: int | None = None
         L = synth.make(spec, "uniform_f32")
         M = p3.Matrix(L)
         res, best = p3.pars3_autotune(M.h, grid=grid, k=1, reps=reps)
-        F.append(M.features())
+        F.append(features_of(M))
         Tm.append([r["us"] for r in res])
         info = M.info()
         meta.append((start + q, FAMILIES.index(spec["family"]), L.n, L.nnz, info["beta"]))
         M.close()
         print(f"[sweep] {start + q} {spec['family']} n={L.n} nnz={L.nnz} best={best} "
               f"us={res[best]['us']:.1f} elapsed={time.time() - t0:.0f}s", file=log, flush=True)
+    return {"features": np.array(F, np.float64), "times_us": np.array(Tm, np.float64),
+            "meta": np.array(meta, np.int64), "grid": grid_table(grid)}
+
+
+def extend(start: int, count: int, reps: int = 10, value_dtype: int | None = None, base: str = DATA,
+           log=sys.stdout) -> dict:
+    """The 3 conflict features and the full-CSR timing of the matrices
+    [start, start + count) of a sweep file without them; the rows of the
+    result replace the file's (its 40 tile timings kept)."""
+    import synth
+    import paper_2407_17651_amd as p3
+
+    vd = p3.F32 if value_dtype is None else value_dtype
+    grid = p3.pars3_tune_grid_default(vd)
+    csr = [g for g in grid if g.engine == p3.ENGINE_CSR]
+    old = load(base)
+    specs = synth.selector_specs(N_MATRICES)
+    F, Tm, meta = [], [], []
+    t0 = time.time()
+    for q in range(start, min(start + count, len(old["meta"]))):
+        idx = int(old["meta"][q, 0])
+        L = synth.make(specs[idx], "uniform_f32")
+        M = p3.Matrix(L).reorder(value_dtype=vd)
+        cf = M.conflict_features()
+        res, _ = p3.pars3_autotune(M.h, grid=(p3.SplitParams * 1)(*csr), k=1, reps=reps)
+        F.append(np.concatenate([old["features"][q, :32], cf]))
+        Tm.append(np.concatenate([old["times_us"][q, :40], [res[0]["us"]]]))
+        meta.append(old["meta"][q])
+        tb = old["times_us"][q, :40]
+        print(f"[extend] {idx} {specs[idx]['family']} n={L.n} csr_us={res[0]['us']:.1f} "
+              f"best_tile_us={tb[tb > 0].min():.1f} elapsed={time.time() - t0:.0f}s", file=log, flush=True)
+        M.close()
     return {"features": np.array(F, np.float64), "times_us": np.array(Tm, np.float64),
             "meta": np.array(meta, np.int64), "grid": grid_table(grid)}
 
@@ -121,9 +172,10 @@ def train(features, times_us, epochs: int = 400, batch: int = 128, lr: float = 2
 
     T, Mk = targets(times_us)
     dev = torch.device("cuda:0")
+    # row-major copies: column selections (fancy indexing) give Fortran order
     X = torch.from_numpy(np.ascontiguousarray(features, np.float32)).to(dev)
-    Td = torch.from_numpy(T).to(dev)
-    Md = torch.from_numpy(Mk).to(dev)
+    Td = torch.from_numpy(np.ascontiguousarray(T)).to(dev)
+    Md = torch.from_numpy(np.ascontiguousarray(Mk)).to(dev)
     mlp = p3.MLP(features.shape[1], hidden[0], hidden[1], T.shape[1], seed)
     mlp.fit_scaler(X)
     hist = mlp.train(X, Td, Md, batch=batch, epochs=epochs, lr=lr, seed=seed)
@@ -144,28 +196,54 @@ def summary(r):
             "within_2pct": float((r <= 0.02).mean())}
 
 
-def evaluate(d=None, epochs: int = 400, seed: int = 7):
-    """Trains on the first matrices, scores regret on the held-out ones."""
+def select(mlp, features, valid):
+    """The network's choice per row of features (device inference)."""
     import torch
 
+    X = torch.from_numpy(np.ascontiguousarray(features, np.float32)).to("cuda:0")
+    V = torch.from_numpy(np.ascontiguousarray(valid, np.float32)).to("cuda:0")
+    return mlp.select_rows(X, V).cpu().numpy()
+
+
+def evaluate(d=None, epochs: int = 400, seed: int = 7, ablations: bool = True):
+    """Trains on the first matrices, scores regret on the held-out ones
+    against the best of every configuration (the 40 tile configurations and
+    the full-CSR engine).  Ablations: the same network without the 3
+    conflict features (32 inputs), without the full-CSR choice (40 outputs),
+    and without both (the selector as it was before either)."""
     d = load() if d is None else d
     tr, te = split(d)
-    mlp, hist = train(d["features"][tr], d["times_us"][tr], epochs=epochs, seed=seed)
-    X = torch.from_numpy(np.ascontiguousarray(d["features"][te], np.float32)).to("cuda:0")
-    valid = torch.from_numpy((d["times_us"][te] > 0).astype(np.float32)).to("cuda:0")
-    choice = mlp.select_rows(X, valid).cpu().numpy()
+    F, T = d["features"], d["times_us"]
+    te_t = T[te]
     grid = d["grid"]
-    paper = int(np.flatnonzero((grid[:, 0] == 256) & (grid[:, 1] == 0) & (grid[:, 2] == -1))[0])
-    single = int(np.argmin(regrets_all(d["times_us"][tr]).mean(0)))
-    te_t = d["times_us"][te]
+    tiles = np.flatnonzero(grid[:, 3] == 0) if grid.shape[1] > 3 else np.arange(grid.shape[0])
+    mlp, hist = train(F[tr], T[tr], epochs=epochs, seed=seed)
+    choice = select(mlp, F[te], te_t > 0)
+    paper = paper_index(grid)
+    single = int(np.argmin(regrets_all(T[tr]).mean(0)))
     out = {
         "held_out": int(te.sum()), "trained_on": int(tr.sum()), "epochs": epochs,
+        "inputs": int(F.shape[1]), "outputs": int(T.shape[1]),
         "final_loss": float(hist[-1]) if len(hist) else None,
         "mlp": summary(regrets(te_t, choice)),
         "paper_default": summary(regrets(te_t, np.full(len(te_t), paper))),
         "best_single": summary(regrets(te_t, np.full(len(te_t), single))),
         "best_single_config": grid[single].tolist(), "paper_config": grid[paper].tolist(),
+        "held_out_csr_chosen": int(np.isin(choice, np.flatnonzero(grid[:, 3] == 1)).sum()) if grid.shape[1] > 3 else 0,
+        "held_out_csr_best": int((np.argmin(np.where(te_t > 0, te_t, np.inf), 1)[:, None]
+                                  == np.flatnonzero(grid[:, 3] == 1)[None, :]).any(1).sum())
+        if grid.shape[1] > 3 else 0,
     }
+    if ablations and len(tiles) < T.shape[1]:
+        variants = {"no_conflict_features": (slice(0, 32), np.arange(T.shape[1])),
+                    "no_csr_choice": (slice(None), tiles),
+                    "neither": (slice(0, 32), tiles)}
+        for name, (fc, gc) in variants.items():
+            m2, _ = train(F[tr][:, fc], T[tr][:, gc], epochs=epochs, seed=seed)
+            c2 = gc[select(m2, F[te][:, fc], te_t[:, gc] > 0)]
+            r_all = regrets(te_t, c2)
+            r_tiles = regrets(te_t[:, tiles], np.searchsorted(tiles, c2)) if np.all(np.isin(c2, tiles)) else None
+            out[name] = {"vs_all": summary(r_all), "vs_tiles": summary(r_tiles) if r_tiles is not None else None}
     return out, mlp
 
 
@@ -239,6 +317,12 @@ def main(argv=None):
     s.add_argument("--count", type=int, default=N_MATRICES)
     s.add_argument("--reps", type=int, default=10)
     s.add_argument("--out", required=True)
+    x = sub.add_parser("extend")
+    x.add_argument("--start", type=int, default=0)
+    x.add_argument("--count", type=int, default=N_MATRICES)
+    x.add_argument("--reps", type=int, default=10)
+    x.add_argument("--base", default=DATA)
+    x.add_argument("--out", required=True)
     m = sub.add_parser("merge")
     m.add_argument("out")
     m.add_argument("inputs", nargs="+")
@@ -258,6 +342,11 @@ def main(argv=None):
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
         np.savez_compressed(a.out, **d)
         print(f"[sweep] wrote {a.out}", flush=True)
+    elif a.cmd == "extend":
+        d = extend(a.start, a.count, a.reps, base=a.base)
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        np.savez_compressed(a.out, **d)
+        print(f"[extend] wrote {a.out}", flush=True)
     elif a.cmd == "merge":
         print(merge(a.inputs, a.out))
     elif a.cmd == "train-save":

@@ -81,4 +81,17 @@ def test_validation_on_generated_inputs(L):
 
 def test_split_params_default(L):
     p = p3.pars3_split_params_default()
-    assert (p.w_in, p.t_out, p.tile_rows, p.permute, p.value_dtype, p.keep_fp64) == (-1, -1, 256, 1, p3.F64, 0)
+    assert (p.w_in, p.t_out, p.tile_rows, p.permute, p.value_dtype, p.keep_fp64, p.engine) == \
+        (-1, -1, 256, 1, p3.F64, 0, p3.ENGINE_TILES)
+
+
+def test_binding_refuses_non_row_major_arrays():
+    """A column selection of a row-major array is Fortran-ordered; the library
+    reads row-major data, so the binding refuses it rather than pass a
+    pointer to differently laid-out memory."""
+    a = np.zeros((4, 3), np.float32)
+    with pytest.raises(ValueError):
+        p3._ptr(np.zeros((4, 41))[:, np.arange(41)])
+    with pytest.raises(ValueError):
+        p3._ptr(np.asfortranarray(a))
+    assert p3._ptr(a) == a.ctypes.data and p3._ptr(np.zeros(0)) is None

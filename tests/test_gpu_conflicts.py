@@ -92,3 +92,33 @@ def test_workload1_full_size():
     nt = -(-L.n // 256)
     tiles = np.minimum(np.arange(nt + 1) * 256, L.n)
     assert np.array_equal(M.conflict_map(nt, tiles), oracle.conflict_map(B, part, nt, tiles))
+
+
+@pytest.mark.parametrize("name,maker", [
+    ("rgg_20000", lambda: synth.rgg2d(20000, 12.0, 8)),
+    ("grid3d_24", lambda: synth.grid3d(24, 3, "normal")),
+    ("chung_lu_8000", lambda: synth.chung_lu(8000, 10.0, 2.5, 5)),
+    ("path_80", lambda: synth.from_edges(80, [(i, i + 1) for i in range(79)], relabel=True, seed=2)),
+    ("no_edges", lambda: synth.from_edges(50, [])),
+])
+@pytest.mark.parametrize("nb", [1, 8, 37])
+def test_conflict_features_bit_exact(name, maker, nb):
+    """The selector's conflict features equal the oracle's on the oracle's
+    reordering, bit for bit (ratios of equal integer counts)."""
+    L = maker()
+    print(f"[gpu] conflict features {name} nb={nb}", flush=True)
+    M = p3.Matrix(L).reorder()
+    want = oracle.conflict_features(oracle.permute(L, oracle.rcm(L)), nb)
+    assert np.array_equal(M.conflict_features(nb), want)
+
+
+def test_conflict_features_errors():
+    L = synth.grid2d(10, 1)
+    M = p3.Matrix(L)
+    with pytest.raises(p3.Pars3Error) as e:
+        M.conflict_features(8)
+    assert e.value.status == p3.ESTATE
+    M.reorder()
+    with pytest.raises(p3.Pars3Error) as e:
+        M.conflict_features(0)
+    assert e.value.status == p3.EINVAL

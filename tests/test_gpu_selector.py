@@ -25,18 +25,26 @@ def data():
 
 
 def test_sweep_records_shape(data):
-    assert data["features"].shape == (selector.N_MATRICES, 32)
-    assert data["times_us"].shape == (selector.N_MATRICES, 40)
+    assert data["features"].shape == (selector.N_MATRICES, 35)
+    assert data["times_us"].shape == (selector.N_MATRICES, 41)
     assert np.all(data["times_us"] > 0)
     assert np.array_equal(data["meta"][:, 0], np.arange(selector.N_MATRICES))
+    g = data["grid"]
+    assert g.shape == (41, 4) and g[40, 3] == p3.ENGINE_CSR and np.all(g[:40, 3] == p3.ENGINE_TILES)
 
 
-def test_selector_beats_paper_default_and_best_single(data):
+def test_selector_beats_paper_default_best_single_and_the_ablations(data):
+    """Regret against the best of all 41 configurations: the network (35
+    inputs, 41 outputs) beats the paper's configuration, the best single
+    configuration, and the same network trained without the full-CSR choice
+    (which cannot route power-law matrices away from the split)."""
     out, _ = selector.evaluate(data, epochs=300)
     print("[gpu] selector " + json.dumps(out), flush=True)
     assert out["held_out"] == selector.N_HELD_OUT
     assert out["mlp"]["mean"] < out["paper_default"]["mean"]
     assert out["mlp"]["mean"] < out["best_single"]["mean"]
+    assert out["mlp"]["mean"] < out["no_csr_choice"]["vs_all"]["mean"]
+    assert out["mlp"]["mean"] < out["neither"]["vs_all"]["mean"]
 
 
 def test_saved_network_selects_well(data):
@@ -47,13 +55,13 @@ def test_saved_network_selects_well(data):
     choice = net.select_rows(X).cpu().numpy()
     r = selector.regrets(data["times_us"][te], choice)
     g = data["grid"]
-    paper = int(np.flatnonzero((g[:, 0] == 256) & (g[:, 1] == 0) & (g[:, 2] == -1))[0])
+    paper = selector.paper_index(g)
     rp = selector.regrets(data["times_us"][te], np.full(len(choice), paper))
     assert r.mean() < rp.mean()
 
 
 def _grid_tuple(g):
-    return (g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute)
+    return (g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute, g.engine)
 
 
 def test_model_file_round_trip_and_selection_through_the_c_abi(tmp_path):
@@ -101,6 +109,7 @@ def test_reorder_without_parameters_uses_the_network_in_use(tmp_path):
         assert A.info() == want
         g = grid[c]
         assert want["tile_rows"] == g.tile_rows and want["value_dtype"] == g.value_dtype
+        assert want["engine"] == g.engine
     finally:
         p3.pars3_model_use(None)
     D = p3.Matrix(L)
@@ -117,7 +126,7 @@ def test_reorder_without_parameters_uses_the_network_in_use(tmp_path):
 
 
 def test_model_save_needs_a_grid(tmp_path):
-    net = p3.MLP(32, 8, 8, 40, seed=3)
+    net = p3.MLP(35, 8, 8, 41, seed=3)
     with pytest.raises(p3.Pars3Error) as e:
         net.save(str(tmp_path / "x.p3mlp"))
     assert e.value.status == p3.ESTATE

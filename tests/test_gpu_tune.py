@@ -12,11 +12,19 @@ from gpu_util import gpu_spmv, oracle_reordered, rel_inf
 pytestmark = pytest.mark.gpu
 
 
-def test_default_grid():
-    g = p3.pars3_tune_grid_default(p3.F64)
-    assert len(g) == 40
-    assert {(c.tile_rows, c.w_in, c.t_out) for c in g} == {
+@pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32, p3.BF16])
+def test_default_grid(value_dtype):
+    """40 tile configurations, then the full-CSR engine (FP64 and FP32 values
+    only)."""
+    g = p3.pars3_tune_grid_default(value_dtype)
+    tiles = [c for c in g if c.engine == p3.ENGINE_TILES]
+    assert len(tiles) == 40
+    assert {(c.tile_rows, c.w_in, c.t_out) for c in tiles} == {
         (T, w, t) for T in (64, 128, 256, 512, 1024) for w in (0, 1, 2, 4) for t in (-1, -2)}
+    if value_dtype == p3.BF16:
+        assert len(g) == 40
+    else:
+        assert len(g) == 41 and g[40].engine == p3.ENGINE_CSR and g[40].value_dtype == value_dtype
 
 
 @pytest.mark.parametrize("value_dtype", [p3.F64, p3.F32, p3.BF16])

@@ -18,11 +18,13 @@ def fnv1a64(data: bytes) -> int:
     return h
 
 
-def model_bytes(sizes, grid, mean, std, params, version=1, magic=b"PARS3MLP"):
+def model_bytes(sizes, grid, mean, std, params, version=2, magic=b"PARS3MLP"):
+    """Version 2 stores 7 split parameters per configuration (the last is the
+    engine); version 1 stored the first 6."""
     n_in, h1, h2, n_out = sizes
     body = magic + struct.pack("<I", version) + struct.pack("<5i", n_in, h1, h2, n_out, len(grid))
     for g in grid:
-        body += struct.pack("<6i", *g)
+        body += struct.pack("<7i", *g) if version == 2 else struct.pack("<6i", *g[:6])
     body += np.asarray(mean, "<f4").tobytes() + np.asarray(std, "<f4").tobytes() + np.asarray(params, "<f4").tobytes()
     return body + struct.pack("<Q", fnv1a64(body))
 
@@ -31,7 +33,7 @@ def example(seed=4, sizes=(32, 8, 6, 5)):
     rng = np.random.default_rng(seed)
     n_in, h1, h2, n_out = sizes
     npar = n_in * h1 + h1 + h1 * h2 + h2 + h2 * n_out + n_out
-    grid = [(w, -1, t, 1, 0, 1) for w, t in zip(range(n_out), (64, 128, 256, 512, 1024))]
+    grid = [(w, -1, t, 1, 0, 1, int(t == 1024)) for w, t in zip(range(n_out), (64, 128, 256, 512, 1024))]
     return sizes, grid, rng.normal(size=n_in), rng.uniform(0.5, 2, n_in), rng.normal(size=npar)
 
 
@@ -48,7 +50,7 @@ def test_damaged_files_are_refused(tmp_path, damage):
     if damage == "magic":
         b = model_bytes(sizes, grid, mean, std, params, magic=b"PARS3MLQ")
     elif damage == "version":
-        b = model_bytes(sizes, grid, mean, std, params, version=2)
+        b = model_bytes(sizes, grid, mean, std, params, version=3)
     elif damage == "truncated":
         b = b[:-20]
     elif damage == "checksum":
@@ -78,9 +80,28 @@ def test_file_written_from_the_description_loads(tmp_path):
     assert np.array_equal(got, np.asarray(params, np.float32))
     mu, sd = m.get_scaler()
     assert np.array_equal(mu, np.asarray(mean, np.float32)) and np.array_equal(sd, np.asarray(std, np.float32))
-    assert [(g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute) for g in m.get_grid()] == grid
+    assert [(g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute, g.engine)
+            for g in m.get_grid()] == grid
     # and the library writes the same bytes back
     out = str(tmp_path / "again.p3mlp")
     m.save(out)
     with open(path, "rb") as a, open(out, "rb") as b:
         assert a.read() == b.read()
+
+
+@pytest.mark.gpu
+def test_version1_file_loads_with_tile_engine(tmp_path):
+    """A version 1 file (6 split parameters per configuration) loads with
+    engine PARS3_ENGINE_TILES everywhere and is written back as version 2."""
+    sizes, grid, mean, std, params = example()
+    grid1 = [g[:6] + (0,) for g in grid]
+    path = str(tmp_path / "v1.p3mlp")
+    with open(path, "wb") as f:
+        f.write(model_bytes(sizes, grid1, mean, std, params, version=1))
+    m = p3.MLP.load(path)
+    assert [(g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute, g.engine)
+            for g in m.get_grid()] == grid1
+    out = str(tmp_path / "v2.p3mlp")
+    m.save(out)
+    with open(out, "rb") as f:
+        assert f.read() == model_bytes(sizes, grid1, mean, std, params, version=2)

@@ -100,3 +100,57 @@ def test_bad_bounds():
     for nb, b in ((0, None), (2, [0, 3, 24]), (2, [1, 3, 25]), (3, [0, 5, 4, 25])):
         with pytest.raises(ValueError):
             oracle.conflict_map(L, part, nb, b)
+
+
+# ---- conflict features over balanced blocks (the selector's inputs 33-35)
+def brute_features(L, nb):
+    """The three ratios from their definitions, with Python sets."""
+    n = L.n
+    bounds = [(p * n) // nb for p in range(nb + 1)]
+    rows_of = np.repeat(np.arange(n), np.diff(L.rowptr))
+    conf, halo, reach = 0, 0.0, 0.0
+    for p in range(nb):
+        lo, hi = bounds[p], bounds[p + 1]
+        rows = max(hi - lo, 1)
+        cols = [int(L.col[e]) for e in np.flatnonzero((rows_of >= lo) & (rows_of < hi)) if L.col[e] < lo]
+        conf += len(cols)
+        halo = max(halo, len(set(cols)) / rows)
+        reach = max(reach, (lo - min(cols)) / rows if cols else 0.0)
+    return np.array([conf / L.nnz if L.nnz else 0.0, halo, reach])
+
+
+def test_features_path_graph_closed_form():
+    """A path of 80 nodes in 8 blocks of 10 rows: each block but the first
+    has one conflicting entry, the edge into the block before it, with one
+    halo column one row back."""
+    L = synth.from_edges(80, [(i, i + 1) for i in range(79)])
+    f = oracle.conflict_features(L, 8)
+    assert f[0] == 7 / 79 and f[1] == 1 / 10 and f[2] == 1 / 10
+
+
+def test_features_complete_graph_closed_form():
+    """K_16 in 8 blocks of 2 rows: block p has 4p conflicting entries over
+    2p halo columns reaching back to column 0, so the largest halo and reach
+    per row are both 14 / 2 = 7 and 112 of the 120 entries conflict."""
+    L = synth.from_edges(16, [(i, j) for i in range(16) for j in range(i + 1, 16)])
+    f = oracle.conflict_features(L, 8)
+    assert f[0] == 112 / 120 and f[1] == 7.0 and f[2] == 7.0
+
+
+def test_features_empty_and_single_block():
+    L = synth.from_edges(40, [])
+    assert np.array_equal(oracle.conflict_features(L, 8), np.zeros(3))
+    G = synth.grid2d(12, 3)
+    assert np.array_equal(oracle.conflict_features(G, 1), np.zeros(3))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("nb", [3, 8])
+def test_features_brute_force(seed, nb):
+    for L in (synth.rgg2d(600, 8.0, seed), synth.chung_lu(500, 6.0, 2.5, seed), synth.grid2d(20, seed)):
+        assert np.allclose(oracle.conflict_features(L, nb), brute_features(L, nb), rtol=0, atol=0)
+
+
+def test_features_bad_block_count():
+    with pytest.raises(ValueError):
+        oracle.conflict_features(synth.grid2d(5, 1), 0)
