@@ -348,3 +348,40 @@ def conflict_features(L, nblocks: int = 8) -> np.ndarray:
     if r != 0:
         raise MemoryError("or_conflict_features")
     return f
+
+
+def lds_passes_sorted(L, tile_rows: int = 256, w_in: int = -1, t_out: int = -1):
+    """LDS bank passes of the product's block entries in sorted order -- a
+    property of the GPU layout's bank model, not of the paper's method (pinned
+    by closed forms in the tests).  The middle and outer entries of L (in the
+    numbering L is given in; split as ``split``) form tile-pair blocks (row
+    tile, part, column tile), each sorted by block diagonal (column offset -
+    row offset mod tile_rows) and then row offset.  Each block is cut into
+    aligned runs of 32 entries; a run takes as many passes as its most
+    frequent row offset mod 32 plus its most frequent column offset mod 32.
+    Returns (runs, passes)."""
+    n, rp, c, _ = _arrs(L)
+    part, _, _ = split(L, w_in, t_out)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    cols = c.astype(np.int64)
+    keep = part != 0
+    if not keep.any():
+        return 0, 0
+    T = int(tile_rows)
+    r, cc, p = rows[keep], cols[keep], part[keep].astype(np.int64)
+    t, u, ri, cj = r // T, cc // T, r % T, cc % T
+    g = (cj - ri) % T
+    order = np.lexsort((ri, g, u, p, t))
+    t, p, u, ri, cj = t[order], p[order], u[order], ri[order], cj[order]
+    new_block = np.r_[True, (t[1:] != t[:-1]) | (p[1:] != p[:-1]) | (u[1:] != u[:-1])]
+    block = np.cumsum(new_block) - 1
+    first = np.flatnonzero(new_block)
+    pos = np.arange(len(ri)) - first[block]
+    run = np.unique(np.stack([block, pos // 32]), axis=1, return_inverse=True)[1].ravel()
+    runs = int(run.max()) + 1
+    passes = 0
+    for cls in (ri % 32, cj % 32):
+        key = run * 32 + cls
+        cnt = np.bincount(key, minlength=runs * 32).reshape(runs, 32)
+        passes += int(cnt.max(axis=1).sum())
+    return runs, passes

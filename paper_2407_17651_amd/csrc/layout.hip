@@ -116,6 +116,344 @@ __global__ void k_block_flags(const uint64_t *__restrict__ keys, int64_t m, int 
   const uint64_t b = keys[q] >> (2 * lgT);
   flag[q] = (q == 0 || (keys[q - 1] >> (2 * lgT)) != b) ? 1 : 0;
 }
+// ---- entry order inside a block, for LDS adds without bank conflicts
+// The product adds each entry's products into the LDS row sum of its row
+// offset (row side) or column offset (column side).  A wavefront's FP64 LDS
+// add is served as two halves of 32 lanes, and two lanes of one half whose
+// offsets agree modulo 32 hit the same bank pair, for every LDS row stride the
+// kernels use (1, 3, 5 and 9 words: all odd), so such a half takes two or more
+// passes.  Chunks start at multiples of 64 entries from the block start, so
+// the halves are the aligned runs of 32 entries of a block.  The sort leaves
+// a block in diagonal order, where runs along one diagonal have distinct row
+// and column offsets; sparse diagonals mix into a half and collide.  Here each
+// half of a block is refilled as a matching between row classes (offset mod
+// 32) and column classes: entries are bucketed by (row class, column class);
+// per half, rows propose to their most loaded free column class, columns
+// accept the most loaded row class, augmenting paths complete the matching,
+// and a class is allowed a second (third, ...) entry only when no matching
+// covers the half.  Each (row, column) class pair gives its entries in
+// diagonal order and a half keeps the order of the sort.  Mixing entries from
+// all over the block spreads the x gathers of a half over more cache lines,
+// so a block keeps the new order only if it costs less (bo_cost: passes
+// against gather spread) than the sorted one: sparse, irregular blocks take
+// it, blocks of dense diagonal runs (stencils) mostly keep the sorted order.  One 64-thread workgroup per block; lanes 0-31 stand for the
+// row classes, lanes 32-63 for the column classes.
+static constexpr int BO_NB = 32 * 32;
+
+__device__ __forceinline__ int bo_bucket(uint64_t k, int lgT) {
+  const uint32_t T1 = (1u << lgT) - 1u;
+  const uint32_t ri = (uint32_t)k & T1, cj = ((uint32_t)(k >> lgT) + ri) & T1;
+  return (int)(((ri & 31u) << 5) | (cj & 31u));
+}
+__device__ __forceinline__ uint32_t bo_or(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v |= (uint32_t)__shfl_xor((int)v, off, 64);
+  return v;
+}
+__device__ __forceinline__ int bo_max(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+// One half of 32 entries (entry q of lane l & 31, or q < 0 for none): its
+// LDS passes (row side + column side: the most loaded row class plus the
+// most loaded column class) and the 16-row units of x its gathers touch on
+// both sides.  Lanes 0-31 look at the row offsets (the row side's LDS slot,
+// the column side's x row), lanes 32-63 at the column offsets.
+struct bo_half {
+  int passes, units;
+};
+// The cost that decides between the two orders of a block: BO_PASS_WEIGHT x
+// passes + units.  The weight is a measured exchange rate: on the batched
+// 8-right-hand-side product (256 matrices), weights of 3, 5 and 10 took
+// 0.532, 0.510 and 0.494 ms per launch.
+static constexpr int BO_PASS_WEIGHT = 10;
+__device__ __forceinline__ int bo_cost(bo_half h) { return BO_PASS_WEIGHT * h.passes + h.units; }
+__device__ __forceinline__ bo_half bo_half_eval(const uint64_t *__restrict__ keys, int32_t q, int lgT, int lane) {
+  const uint32_t T1 = (1u << lgT) - 1u;
+  int o = -1;
+  if (q >= 0) {
+    const uint64_t k = keys[q];
+    const uint32_t ri = (uint32_t)k & T1, cj = ((uint32_t)(k >> lgT) + ri) & T1;
+    o = (int)(lane < 32 ? ri : cj);
+  }
+  int mult = 0;
+  bool first = o >= 0;
+  for (int j = 0; j < 32; j++) {
+    const int oj = __shfl(o, (lane & 32) | j, 64);
+    mult += (o >= 0) & (oj >= 0) & ((oj & 31) == (o & 31));
+    first &= !(j < (lane & 31) && oj >= 0 && (oj >> 4) == (o >> 4));
+  }
+  bo_half h;
+  h.passes = bo_max(lane < 32 ? mult : 0) + bo_max(lane < 32 ? 0 : mult);
+  h.units = (int)__popcll(__ballot(first));
+  return h;
+}
+
+__global__ __launch_bounds__(64) void k_bank_order(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                                   const int32_t *__restrict__ bstart, int lgT,
+                                                   uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+                                                   int32_t *__restrict__ lst, int32_t *__restrict__ stats) {
+  __shared__ int32_t head[BO_NB], tail[BO_NB];
+  __shared__ int32_t s_rem[64], s_mate[64], s_par[32], s_prop[32], s_grp[32];
+  const int lane = threadIdx.x;
+  const int cls = lane & 31;
+  const bool isrow = lane < 32;
+  const int32_t s = bstart[blockIdx.x], e = bstart[blockIdx.x + 1];
+  int32_t *st = stats + 3 * (int64_t)blockIdx.x;  // halves, passes of the sorted order, passes kept
+  if (e - s <= 32) {
+    const bo_half h = bo_half_eval(keys, s + cls < e ? s + cls : -1, lgT, lane);
+    for (int32_t q = s + lane; q < e; q += 64) {
+      keys_out[q] = keys[q];
+      vals_out[q] = vals[q];
+    }
+    if (lane == 0) {
+      st[0] = 1;
+      st[1] = h.passes;
+      st[2] = h.passes;
+    }
+    return;
+  }
+  // bucket sizes, their starts (exclusive scan, 16 buckets per lane), and
+  // the stable bucket lists (entry positions in sorted order)
+  for (int i = lane; i < BO_NB; i += 64) head[i] = 0;
+  __syncthreads();
+  for (int32_t q = s + lane; q < e; q += 64) atomicAdd(&head[bo_bucket(keys[q], lgT)], 1);
+  __syncthreads();
+  int32_t c16[16], tot = 0;
+#pragma unroll
+  for (int u = 0; u < 16; u++) {
+    c16[u] = head[lane * 16 + u];
+    tot += c16[u];
+  }
+  int32_t incl = tot;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t v = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += v;
+  }
+  int32_t run = incl - tot;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; u++) {
+    head[lane * 16 + u] = run;
+    tail[lane * 16 + u] = run;
+    run += c16[u];
+  }
+  __syncthreads();
+  int32_t cost_orig = 0, pass_orig = 0, halves = 0;
+  for (int32_t q0 = s; q0 < e; q0 += 64) {
+    const int32_t q = q0 + lane;
+    const int bk = q < e ? bo_bucket(keys[q], lgT) : -1;
+    int rank = 0;
+    for (int j = 0; j < 64; j++) {
+      const int bj = __shfl(bk, j, 64);
+      rank += (j < lane) & (bj == bk);
+    }
+    const int32_t base = bk >= 0 ? tail[bk] : 0;
+    __syncthreads();
+    if (bk >= 0) {
+      lst[s + base + rank] = q;
+      atomicAdd(&tail[bk], 1);
+    }
+    __syncthreads();
+    // cost of the sorted order, for its two halves
+    for (int h = 0; h < 2; h++) {
+      const int32_t qh = q0 + 32 * h + cls;
+      if (q0 + 32 * h < e) {
+        const bo_half hv = bo_half_eval(keys, qh < e ? qh : -1, lgT, lane);
+        cost_orig += bo_cost(hv);
+        pass_orig += hv.passes;
+        halves++;
+      }
+    }
+  }
+  // per lane: the class's nonempty partner classes and its entry count
+  uint32_t adj = 0;
+  int32_t rem = 0;
+  for (int o = 0; o < 32; o++) {
+    const int bk = isrow ? (cls << 5 | o) : (o << 5 | cls);
+    const int32_t c = tail[bk] - head[bk];
+    rem += c;
+    if (c) adj |= 1u << o;
+  }
+  s_rem[lane] = rem;
+  __syncthreads();
+  int32_t cost_new = 0, pass_new = 0;
+  bool fail = false;  // a half that could not be filled (not expected): keep the sorted order
+  for (int32_t out = s; out < e && !fail;) {
+    const int need = min(32, (int)(e - out));
+    int cnt = 0;  // entries of this lane's class in the half
+    int got = 0;
+    // a class limit of 33 admits every remaining entry, so the loop ends by then
+    for (int lim = 1; got < need && lim <= 40; lim++) {
+      const uint64_t okm = __ballot(cnt < lim);
+      const uint32_t rows_ok = (uint32_t)okm, cols_ok = (uint32_t)(okm >> 32);
+      const bool ok = cnt < lim;
+      int mate = -1;
+      // greedy: unmatched rows propose to their most loaded free column, each
+      // column takes the most loaded proposer
+      for (int round = 0; round < 32; round++) {
+        const uint32_t mcols = (uint32_t)(__ballot(!isrow && mate >= 0) >> 32);
+        int prop = -1;
+        if (isrow && ok && mate < 0) {
+          uint32_t av = adj & cols_ok & ~mcols;
+          int32_t best = -1;
+          while (av) {
+            const int c = __ffs(av) - 1;
+            av &= av - 1u;
+            const int32_t v = s_rem[32 + c];
+            if (v > best) {
+              best = v;
+              prop = c;
+            }
+          }
+        }
+        if (!__ballot(prop >= 0)) break;
+        if (isrow) s_prop[cls] = prop;
+        __syncthreads();
+        if (!isrow && ok && mate < 0) {
+          int32_t best = -1;
+          for (int r = 0; r < 32; r++)
+            if (s_prop[r] == cls && s_rem[r] > best) {
+              best = s_rem[r];
+              mate = r;
+            }
+        }
+        if (!isrow) s_mate[lane] = mate;
+        __syncthreads();
+        if (isrow && prop >= 0 && s_mate[32 + prop] == cls) mate = prop;
+        __syncthreads();
+      }
+      // augmenting paths from the remaining free rows
+      uint32_t tried = 0;
+      for (;;) {
+        const uint32_t mrows = (uint32_t)__ballot(isrow && mate >= 0);
+        if (got + __popc(mrows) >= need) break;
+        const uint32_t mcols = (uint32_t)(__ballot(!isrow && mate >= 0) >> 32);
+        const uint32_t cand =
+            (uint32_t)__ballot(isrow && ok && mate < 0 && !((tried >> cls) & 1u) && (adj & cols_ok) != 0u);
+        if (!cand) break;
+        const int r0 = __ffs(cand) - 1;
+        tried |= 1u << r0;
+        uint32_t front = 1u << r0, seen = 0;
+        int found = -1;
+        while (front) {
+          uint32_t nb = (isrow && ((front >> cls) & 1u)) ? (adj & cols_ok) : 0u;
+          nb = bo_or(nb) & ~seen;
+          if (!nb) break;
+          if (!isrow && ((nb >> cls) & 1u)) s_par[cls] = __ffs(adj & front) - 1;
+          seen |= nb;
+          const uint32_t freec = nb & ~mcols;
+          if (freec) {
+            found = __ffs(freec) - 1;
+            break;
+          }
+          front = bo_or((!isrow && ((nb >> cls) & 1u)) ? (1u << mate) : 0u);
+        }
+        if (found < 0) continue;
+        s_mate[lane] = mate;
+        __syncthreads();
+        if (lane == 0) {
+          // back along the BFS parents to r0 (at most 32 steps)
+          int c = found;
+          for (int step = 0; step < 33 && c >= 0 && c < 32; step++) {
+            const int r = s_par[c];
+            if (r < 0 || r >= 32) break;
+            const int prev = s_mate[r];
+            s_mate[r] = c;
+            s_mate[32 + c] = r;
+            if (r == r0) break;
+            c = prev;
+          }
+        }
+        __syncthreads();
+        mate = s_mate[lane];
+        __syncthreads();
+      }
+      // take the matched pairs (at most need - got, rows in ascending order)
+      const uint32_t mrows = (uint32_t)__ballot(isrow && mate >= 0);
+      const int take = min(__popc(mrows), need - got);
+      if (take == 0) continue;
+      bool use = false;
+      int slot = 0;
+      if (isrow && mate >= 0) {
+        slot = __popc(mrows & ((1u << cls) - 1u));
+        use = slot < take;
+      }
+      if (isrow) s_prop[cls] = use ? mate : -1;
+      __syncthreads();
+      const bool col_used = !isrow && mate >= 0 && s_prop[mate] == cls;
+      if (use) {
+        const int bk = cls << 5 | mate;
+        const int32_t at = head[bk];
+        head[bk] = at + 1;
+        s_grp[got + slot] = lst[s + at];
+      }
+      __syncthreads();
+      if (use || col_used) {
+        const int bk = isrow ? (cls << 5 | mate) : (mate << 5 | cls);
+        if (head[bk] == tail[bk]) adj &= ~(1u << mate);
+        cnt++;
+        rem--;
+      }
+      s_rem[lane] = rem;
+      __syncthreads();
+      got += take;
+    }
+    if (got < need) {
+      fail = true;
+      break;
+    }
+    {
+      const bo_half hv = bo_half_eval(keys, cls < need ? s_grp[cls] : -1, lgT, lane);
+      cost_new += bo_cost(hv);
+      pass_new += hv.passes;
+    }
+    if (lane < need) {
+      const int32_t v = s_grp[lane];
+      int rank = 0;
+      for (int j = 0; j < need; j++) rank += s_grp[j] < v;
+      keys_out[out + rank] = keys[v];
+      vals_out[out + rank] = vals[v];
+    }
+    __syncthreads();
+    out += need;
+  }
+  __syncthreads();
+  const bool keep = fail || cost_new >= cost_orig;
+  if (keep) {
+    for (int32_t q = s + lane; q < e; q += 64) {
+      keys_out[q] = keys[q];
+      vals_out[q] = vals[q];
+    }
+  }
+  if (lane == 0) {
+    st[0] = halves;
+    st[1] = pass_orig;
+    st[2] = keep ? pass_orig : pass_new;
+  }
+}
+// Sums of the per-block statistics (one workgroup; int64 totals).
+__global__ __launch_bounds__(TB) void k_sum3(const int32_t *__restrict__ a, int32_t nb, long long *__restrict__ out) {
+  __shared__ long long red[3][TB];
+  long long t[3] = {0, 0, 0};
+  for (int32_t b = threadIdx.x; b < nb; b += TB)
+    for (int k = 0; k < 3; k++) t[k] += a[3 * (int64_t)b + k];
+  for (int k = 0; k < 3; k++) red[k][threadIdx.x] = t[k];
+  __syncthreads();
+  for (int w = TB / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 3; k++) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
+}
+__global__ void k_block_starts(const int32_t *__restrict__ flag, const int32_t *__restrict__ bpos, int64_t m,
+                               int32_t *__restrict__ bstart) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m && flag[q]) bstart[bpos[q]] = (int32_t)q;
+}
 __global__ void k_fill_blocks(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t m, int lgT,
                               int tbits, const int32_t *__restrict__ flag, const int32_t *__restrict__ bpos,
                               const double *__restrict__ pval, uint32_t *ent32, uint16_t *ent16, double *ef64,
@@ -345,8 +683,6 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
     P3_LAUNCHED();
   }
   P3_TRY(radix_sort_pairs(k0.p, v0.p, k1.p, v1.p, m, key_bits, s));
-  k1.release();
-  v1.release();
 
   // ---- blocks
   dbuf<int32_t> bflag, bpos, tcount, ucount;
@@ -381,6 +717,32 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   }
   P3_HIP(hipMemcpyAsync(L.blk_start.p + nb, &m32, sizeof(int32_t), hipMemcpyHostToDevice, s));
   if (nnz > 0) P3_TRY(fill_i32(L.pos_of.p, -1, nnz, s));
+  if (m > 0) {
+    // conflict-free halves inside each block: (k0, v0) -> (k1, v1)
+    k_block_starts<<<nblk(m), TB, 0, s>>>(bflag.p, bpos.p, m, L.blk_start.p);
+    P3_LAUNCHED();
+    dbuf<int32_t> lst, bst;
+    dbuf<long long> tot;
+    P3_HIP(lst.alloc(m));
+    P3_HIP(bst.alloc(3 * (size_t)nb));
+    P3_HIP(tot.alloc(3));
+    k_bank_order<<<(unsigned)nb, 64, 0, s>>>(k0.p, v0.p, L.blk_start.p, lgT, k1.p, v1.p, lst.p, bst.p);
+    P3_LAUNCHED();
+    k_sum3<<<1, TB, 0, s>>>(bst.p, nb, tot.p);
+    P3_LAUNCHED();
+    long long h3[3] = {0, 0, 0};
+    P3_HIP(hipMemcpyAsync(h3, tot.p, sizeof(h3), hipMemcpyDeviceToHost, s));
+    P3_HIP(hipStreamSynchronize(s));
+    L.lds_halves = h3[0];
+    L.lds_passes_sorted = h3[1];
+    L.lds_passes = h3[2];
+    std::swap(k0.p, k1.p);
+    std::swap(v0.p, v1.p);
+  } else {
+    L.lds_halves = L.lds_passes_sorted = L.lds_passes = 0;
+  }
+  k1.release();
+  v1.release();
   if (m > 0) {
     k_fill_blocks<<<nblk(m), TB, 0, s>>>(k0.p, v0.p, m, lgT, tbits, bflag.p, bpos.p, A->pval.p, L.ent_rc.p,
                                          L.ent_rc16.p, want64 ? L.ent_f64.p : nullptr,
