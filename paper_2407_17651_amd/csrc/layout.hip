@@ -169,6 +169,9 @@ struct bo_half {
 // 0.532, 0.510 and 0.494 ms per launch.
 static constexpr int BO_PASS_WEIGHT = 10;
 __device__ __forceinline__ int bo_cost(bo_half h) { return BO_PASS_WEIGHT * h.passes + h.units; }
+// Lane src's value of v; src is the same on every lane (v_readlane).
+__device__ __forceinline__ int bo_lane(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
 __device__ __forceinline__ bo_half bo_half_eval(const uint64_t *__restrict__ keys, int32_t q, int lgT, int lane) {
   const uint32_t T1 = (1u << lgT) - 1u;
   int o = -1;
@@ -180,7 +183,8 @@ __device__ __forceinline__ bo_half bo_half_eval(const uint64_t *__restrict__ key
   int mult = 0;
   bool first = o >= 0;
   for (int j = 0; j < 32; j++) {
-    const int oj = __shfl(o, (lane & 32) | j, 64);
+    const int lo = bo_lane(o, j), hi = bo_lane(o, 32 + j);
+    const int oj = lane < 32 ? lo : hi;
     mult += (o >= 0) & (oj >= 0) & ((oj & 31) == (o & 31));
     first &= !(j < (lane & 31) && oj >= 0 && (oj >> 4) == (o >> 4));
   }
@@ -195,233 +199,190 @@ __global__ __launch_bounds__(64) void k_bank_order(const uint64_t *__restrict__ 
                                                    uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
                                                    int32_t *__restrict__ lst, int32_t *__restrict__ stats) {
   __shared__ int32_t head[BO_NB], tail[BO_NB];
-  __shared__ int32_t s_rem[64], s_mate[64], s_par[32], s_prop[32], s_grp[32];
+  __shared__ int32_t s_grp[32];
   const int lane = threadIdx.x;
   const int cls = lane & 31;
   const bool isrow = lane < 32;
   const int32_t s = bstart[blockIdx.x], e = bstart[blockIdx.x + 1];
   int32_t *st = stats + 3 * (int64_t)blockIdx.x;  // halves, passes of the sorted order, passes kept
-  if (e - s <= 32) {
-    const bo_half h = bo_half_eval(keys, s + cls < e ? s + cls : -1, lgT, lane);
-    for (int32_t q = s + lane; q < e; q += 64) {
-      keys_out[q] = keys[q];
-      vals_out[q] = vals[q];
-    }
-    if (lane == 0) {
-      st[0] = 1;
-      st[1] = h.passes;
-      st[2] = h.passes;
-    }
-    return;
-  }
-  // bucket sizes, their starts (exclusive scan, 16 buckets per lane), and
-  // the stable bucket lists (entry positions in sorted order)
-  for (int i = lane; i < BO_NB; i += 64) head[i] = 0;
-  __syncthreads();
-  for (int32_t q = s + lane; q < e; q += 64) atomicAdd(&head[bo_bucket(keys[q], lgT)], 1);
-  __syncthreads();
-  int32_t c16[16], tot = 0;
-#pragma unroll
-  for (int u = 0; u < 16; u++) {
-    c16[u] = head[lane * 16 + u];
-    tot += c16[u];
-  }
-  int32_t incl = tot;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int32_t v = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += v;
-  }
-  int32_t run = incl - tot;
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 16; u++) {
-    head[lane * 16 + u] = run;
-    tail[lane * 16 + u] = run;
-    run += c16[u];
-  }
-  __syncthreads();
+  // the sorted order's cost
   int32_t cost_orig = 0, pass_orig = 0, halves = 0;
-  for (int32_t q0 = s; q0 < e; q0 += 64) {
-    const int32_t q = q0 + lane;
-    const int bk = q < e ? bo_bucket(keys[q], lgT) : -1;
-    int rank = 0;
-    for (int j = 0; j < 64; j++) {
-      const int bj = __shfl(bk, j, 64);
-      rank += (j < lane) & (bj == bk);
-    }
-    const int32_t base = bk >= 0 ? tail[bk] : 0;
+  for (int32_t h0 = s; h0 < e; h0 += 32) {
+    const bo_half hv = bo_half_eval(keys, h0 + cls < e ? h0 + cls : -1, lgT, lane);
+    cost_orig += bo_cost(hv);
+    pass_orig += hv.passes;
+    halves++;
+  }
+  bool keep = halves <= 1 || pass_orig == 2 * halves;  // nothing to gain
+  int32_t pass_new = 0;
+  if (!keep) {
+    // bucket sizes, their starts (exclusive scan, 16 buckets per lane), and
+    // the stable bucket lists (entry positions in sorted order)
+    for (int i = lane; i < BO_NB; i += 64) head[i] = 0;
     __syncthreads();
-    if (bk >= 0) {
-      lst[s + base + rank] = q;
-      atomicAdd(&tail[bk], 1);
+    for (int32_t q = s + lane; q < e; q += 64) atomicAdd(&head[bo_bucket(keys[q], lgT)], 1);
+    __syncthreads();
+    int32_t c16[16], tot = 0;
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+      c16[u] = head[lane * 16 + u];
+      tot += c16[u];
+    }
+    int32_t incl = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t v = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += v;
+    }
+    int32_t run = incl - tot;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+      head[lane * 16 + u] = run;
+      tail[lane * 16 + u] = run;
+      run += c16[u];
     }
     __syncthreads();
-    // cost of the sorted order, for its two halves
-    for (int h = 0; h < 2; h++) {
-      const int32_t qh = q0 + 32 * h + cls;
-      if (q0 + 32 * h < e) {
-        const bo_half hv = bo_half_eval(keys, qh < e ? qh : -1, lgT, lane);
-        cost_orig += bo_cost(hv);
-        pass_orig += hv.passes;
-        halves++;
+    for (int32_t q0 = s; q0 < e; q0 += 64) {
+      const int32_t q = q0 + lane;
+      const int bk = q < e ? bo_bucket(keys[q], lgT) : -1;
+      int rank = 0;
+      for (int j = 0; j < 64; j++) rank += (j < lane) & (bo_lane(bk, j) == bk);
+      const int32_t base = bk >= 0 ? tail[bk] : 0;
+      __syncthreads();
+      if (bk >= 0) {
+        lst[s + base + rank] = q;
+        atomicAdd(&tail[bk], 1);
       }
+      __syncthreads();
     }
-  }
-  // per lane: the class's nonempty partner classes and its entry count
-  uint32_t adj = 0;
-  int32_t rem = 0;
-  for (int o = 0; o < 32; o++) {
-    const int bk = isrow ? (cls << 5 | o) : (o << 5 | cls);
-    const int32_t c = tail[bk] - head[bk];
-    rem += c;
-    if (c) adj |= 1u << o;
-  }
-  s_rem[lane] = rem;
-  __syncthreads();
-  int32_t cost_new = 0, pass_new = 0;
-  bool fail = false;  // a half that could not be filled (not expected): keep the sorted order
-  for (int32_t out = s; out < e && !fail;) {
-    const int need = min(32, (int)(e - out));
-    int cnt = 0;  // entries of this lane's class in the half
-    int got = 0;
-    // a class limit of 33 admits every remaining entry, so the loop ends by then
-    for (int lim = 1; got < need && lim <= 40; lim++) {
-      const uint64_t okm = __ballot(cnt < lim);
-      const uint32_t rows_ok = (uint32_t)okm, cols_ok = (uint32_t)(okm >> 32);
-      const bool ok = cnt < lim;
-      int mate = -1;
-      // greedy: unmatched rows propose to their most loaded free column, each
-      // column takes the most loaded proposer
-      for (int round = 0; round < 32; round++) {
-        const uint32_t mcols = (uint32_t)(__ballot(!isrow && mate >= 0) >> 32);
-        int prop = -1;
-        if (isrow && ok && mate < 0) {
-          uint32_t av = adj & cols_ok & ~mcols;
-          int32_t best = -1;
-          while (av) {
-            const int c = __ffs(av) - 1;
-            av &= av - 1u;
-            const int32_t v = s_rem[32 + c];
-            if (v > best) {
-              best = v;
+    // per lane: its class's nonempty partner classes and its entry count
+    uint32_t adj = 0;
+    int rem = 0;
+    for (int o = 0; o < 32; o++) {
+      const int bk = isrow ? (cls << 5 | o) : (o << 5 | cls);
+      const int32_t c = tail[bk] - head[bk];
+      rem += c;
+      if (c) adj |= 1u << o;
+    }
+    int32_t cost_new = 0;
+    for (int32_t out = s; out < e && !keep;) {
+      const int need = min(32, (int)(e - out));
+      int cnt = 0;  // entries of this lane's class in the half
+      int got = 0;
+      // a class limit of 33 admits every remaining entry, so the loop ends by then
+      for (int lim = 1; got < need && lim <= 40; lim++) {
+        const bool ok = cnt < lim;
+        const uint32_t cols_ok = (uint32_t)(__ballot(ok) >> 32);
+        int mate = -1;
+        // greedy: unmatched rows propose to their most loaded free column,
+        // each column takes its most loaded proposer
+        for (int round = 0; round < 32; round++) {
+          const uint32_t mcols = (uint32_t)(__ballot(!isrow && mate >= 0) >> 32);
+          const uint32_t av = (isrow && ok && mate < 0) ? (adj & cols_ok & ~mcols) : 0u;
+          int prop = -1, best = -1;
+          for (int c = 0; c < 32; c++) {
+            const int rc = bo_lane(rem, 32 + c);
+            if (((av >> c) & 1u) && rc > best) {
+              best = rc;
               prop = c;
             }
           }
-        }
-        if (!__ballot(prop >= 0)) break;
-        if (isrow) s_prop[cls] = prop;
-        __syncthreads();
-        if (!isrow && ok && mate < 0) {
-          int32_t best = -1;
-          for (int r = 0; r < 32; r++)
-            if (s_prop[r] == cls && s_rem[r] > best) {
-              best = s_rem[r];
-              mate = r;
+          if (!__ballot(prop >= 0)) break;
+          int acc = -1, bestr = -1;
+          for (int r = 0; r < 32; r++) {
+            const int pr = bo_lane(prop, r), rr = bo_lane(rem, r);
+            if (pr == cls && rr > bestr) {
+              bestr = rr;
+              acc = r;
             }
-        }
-        if (!isrow) s_mate[lane] = mate;
-        __syncthreads();
-        if (isrow && prop >= 0 && s_mate[32 + prop] == cls) mate = prop;
-        __syncthreads();
-      }
-      // augmenting paths from the remaining free rows
-      uint32_t tried = 0;
-      for (;;) {
-        const uint32_t mrows = (uint32_t)__ballot(isrow && mate >= 0);
-        if (got + __popc(mrows) >= need) break;
-        const uint32_t mcols = (uint32_t)(__ballot(!isrow && mate >= 0) >> 32);
-        const uint32_t cand =
-            (uint32_t)__ballot(isrow && ok && mate < 0 && !((tried >> cls) & 1u) && (adj & cols_ok) != 0u);
-        if (!cand) break;
-        const int r0 = __ffs(cand) - 1;
-        tried |= 1u << r0;
-        uint32_t front = 1u << r0, seen = 0;
-        int found = -1;
-        while (front) {
-          uint32_t nb = (isrow && ((front >> cls) & 1u)) ? (adj & cols_ok) : 0u;
-          nb = bo_or(nb) & ~seen;
-          if (!nb) break;
-          if (!isrow && ((nb >> cls) & 1u)) s_par[cls] = __ffs(adj & front) - 1;
-          seen |= nb;
-          const uint32_t freec = nb & ~mcols;
-          if (freec) {
-            found = __ffs(freec) - 1;
-            break;
           }
-          front = bo_or((!isrow && ((nb >> cls) & 1u)) ? (1u << mate) : 0u);
+          if (!isrow && acc >= 0) mate = acc;
+          const int cm = __shfl(mate, 32 + max(prop, 0), 64);
+          if (isrow && prop >= 0 && cm == cls) mate = prop;
         }
-        if (found < 0) continue;
-        s_mate[lane] = mate;
-        __syncthreads();
-        if (lane == 0) {
-          // back along the BFS parents to r0 (at most 32 steps)
-          int c = found;
-          for (int step = 0; step < 33 && c >= 0 && c < 32; step++) {
-            const int r = s_par[c];
+        // augmenting paths from the remaining free rows (BFS over column
+        // classes; parents kept by the column lanes)
+        uint32_t tried = 0;
+        for (;;) {
+          const uint32_t mrows = (uint32_t)__ballot(isrow && mate >= 0);
+          if (got + __popc(mrows) >= need) break;
+          const uint32_t mcols = (uint32_t)(__ballot(!isrow && mate >= 0) >> 32);
+          const uint32_t cand =
+              (uint32_t)__ballot(isrow && ok && mate < 0 && !((tried >> cls) & 1u) && (adj & cols_ok) != 0u);
+          if (!cand) break;
+          const int r0 = __ffs(cand) - 1;
+          tried |= 1u << r0;
+          uint32_t front = 1u << r0, seen = 0;
+          int found = -1, par = -1;
+          while (front) {
+            uint32_t nb = (isrow && ((front >> cls) & 1u)) ? (adj & cols_ok) : 0u;
+            nb = bo_or(nb) & ~seen;
+            if (!nb) break;
+            if (!isrow && ((nb >> cls) & 1u)) par = __ffs(adj & front) - 1;
+            seen |= nb;
+            const uint32_t freec = nb & ~mcols;
+            if (freec) {
+              found = __ffs(freec) - 1;
+              break;
+            }
+            front = bo_or((!isrow && ((nb >> cls) & 1u)) ? (1u << mate) : 0u);
+          }
+          if (found < 0) continue;
+          // flip the path back to r0 (at most 32 steps; every index is uniform)
+          for (int c = found, step = 0; step < 33 && c >= 0 && c < 32; step++) {
+            const int r = bo_lane(par, 32 + c);
             if (r < 0 || r >= 32) break;
-            const int prev = s_mate[r];
-            s_mate[r] = c;
-            s_mate[32 + c] = r;
+            const int prev = bo_lane(mate, r);
+            if (lane == r) mate = c;
+            if (lane == 32 + c) mate = r;
             if (r == r0) break;
             c = prev;
           }
         }
+        // take the matched pairs (at most need - got, rows in ascending order)
+        const uint32_t mrows = (uint32_t)__ballot(isrow && mate >= 0);
+        const int take = min(__popc(mrows), need - got);
+        if (take == 0) continue;
+        const int slot = isrow ? __popc(mrows & ((1u << cls) - 1u)) : 0;
+        const bool use = isrow && mate >= 0 && slot < take;
+        const int ru = __shfl(use ? mate : -1, max(mate, 0) & 31, 64);
+        const bool col_used = !isrow && mate >= 0 && ru == cls;
+        if (use) {
+          const int bk = cls << 5 | mate;
+          const int32_t at = head[bk];
+          head[bk] = at + 1;
+          s_grp[got + slot] = lst[s + at];
+        }
         __syncthreads();
-        mate = s_mate[lane];
-        __syncthreads();
+        if (use || col_used) {
+          const int bk = isrow ? (cls << 5 | mate) : (mate << 5 | cls);
+          if (head[bk] == tail[bk]) adj &= ~(1u << mate);
+          cnt++;
+          rem--;
+        }
+        got += take;
       }
-      // take the matched pairs (at most need - got, rows in ascending order)
-      const uint32_t mrows = (uint32_t)__ballot(isrow && mate >= 0);
-      const int take = min(__popc(mrows), need - got);
-      if (take == 0) continue;
-      bool use = false;
-      int slot = 0;
-      if (isrow && mate >= 0) {
-        slot = __popc(mrows & ((1u << cls) - 1u));
-        use = slot < take;
-      }
-      if (isrow) s_prop[cls] = use ? mate : -1;
-      __syncthreads();
-      const bool col_used = !isrow && mate >= 0 && s_prop[mate] == cls;
-      if (use) {
-        const int bk = cls << 5 | mate;
-        const int32_t at = head[bk];
-        head[bk] = at + 1;
-        s_grp[got + slot] = lst[s + at];
+      if (got < need) {  // not expected: keep the sorted order
+        keep = true;
+        break;
       }
       __syncthreads();
-      if (use || col_used) {
-        const int bk = isrow ? (cls << 5 | mate) : (mate << 5 | cls);
-        if (head[bk] == tail[bk]) adj &= ~(1u << mate);
-        cnt++;
-        rem--;
-      }
-      s_rem[lane] = rem;
-      __syncthreads();
-      got += take;
-    }
-    if (got < need) {
-      fail = true;
-      break;
-    }
-    {
       const bo_half hv = bo_half_eval(keys, cls < need ? s_grp[cls] : -1, lgT, lane);
       cost_new += bo_cost(hv);
       pass_new += hv.passes;
+      if (cost_new >= cost_orig) keep = true;  // cannot end cheaper any more
+      if (lane < need) {
+        const int32_t v = s_grp[lane];
+        int rank = 0;
+        for (int j = 0; j < need; j++) rank += s_grp[j] < v;
+        keys_out[out + rank] = keys[v];
+        vals_out[out + rank] = vals[v];
+      }
+      __syncthreads();
+      out += need;
     }
-    if (lane < need) {
-      const int32_t v = s_grp[lane];
-      int rank = 0;
-      for (int j = 0; j < need; j++) rank += s_grp[j] < v;
-      keys_out[out + rank] = keys[v];
-      vals_out[out + rank] = vals[v];
-    }
-    __syncthreads();
-    out += need;
   }
-  __syncthreads();
-  const bool keep = fail || cost_new >= cost_orig;
   if (keep) {
     for (int32_t q = s + lane; q < e; q += 64) {
       keys_out[q] = keys[q];
