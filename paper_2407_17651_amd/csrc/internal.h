@@ -301,15 +301,35 @@ struct mrs_dev {
 
 // One step of the rotation recurrence from ||w||^2 (see mrs.hip); run by
 // one thread.  Sets the coefficients of this iteration's vector update
-// (active = 1) or stops the run (done = 1, status).
-__device__ __forceinline__ void mrs_update(mrs_dev *d, int par, double sumsq, double *hist) {
+// (active = 1) or stops the run (done = 1, status).  The state it reads is
+// loaded first (mrs_load), all of it before any store, so that the loads go
+// out together instead of one memory round trip after another.
+struct mrs_in {
+  double beta_j, c1, s1, c2, s2, eta, alpha, nrm, bnorm, tol_abs;
+  int32_t iter, maxit;
+};
+__device__ __forceinline__ mrs_in mrs_load(const mrs_dev *d, int par) {
+  mrs_in in;
+  in.beta_j = d->beta[par];
+  in.c1 = d->c1[par];
+  in.s1 = d->s1[par];
+  in.c2 = d->c2[par];
+  in.s2 = d->s2[par];
+  in.eta = d->eta[par];
+  in.alpha = d->alpha;
+  in.nrm = d->nrm[par];
+  in.bnorm = d->bnorm;
+  in.tol_abs = d->tol_abs;
+  in.iter = d->iter;
+  in.maxit = d->maxit;
+  return in;
+}
+__device__ __forceinline__ void mrs_apply(mrs_dev *d, int par, double sumsq, double *hist, const mrs_in &in) {
   const double beta_n = sqrt(sumsq);
-  const double beta_j = d->beta[par], c1 = d->c1[par], s1 = d->s1[par], c2 = d->c2[par], s2 = d->s2[par];
-  const double eta = d->eta[par], alpha = d->alpha;
-  const double eps = s2 * (-beta_j);
-  const double dbar = c2 * (-beta_j);
-  const double delta = c1 * dbar + s1 * alpha;
-  const double gbar = -s1 * dbar + c1 * alpha;
+  const double eps = in.s2 * (-in.beta_j);
+  const double dbar = in.c2 * (-in.beta_j);
+  const double delta = in.c1 * dbar + in.s1 * in.alpha;
+  const double gbar = -in.s1 * dbar + in.c1 * in.alpha;
   const double gamma = sqrt(gbar * gbar + beta_n * beta_n);
   if (!isfinite(beta_n) || !isfinite(gamma)) {
     d->status = 3;
@@ -324,33 +344,38 @@ __device__ __forceinline__ void mrs_update(mrs_dev *d, int par, double sumsq, do
     return;
   }
   const double c = gbar / gamma, s = beta_n / gamma;
+  const double inv_beta = beta_n > 0.0 ? 1.0 / beta_n : 0.0;
+  const double vnrm_inv = in.nrm > 0.0 ? 1.0 / in.nrm : 0.0;
+  const double eta_n = -s * in.eta;
+  const int32_t it = in.iter + 1;
   d->delta = delta;
   d->eps = eps;
   d->gamma = gamma;
-  d->ceta = c * eta;
-  d->inv_beta = beta_n > 0.0 ? 1.0 / beta_n : 0.0;
-  d->vnrm_inv = d->nrm[par] > 0.0 ? 1.0 / d->nrm[par] : 0.0;
-  d->scaleS = d->inv_beta;
-  d->zcoef = beta_n * d->vnrm_inv;
+  d->ceta = c * in.eta;
+  d->inv_beta = inv_beta;
+  d->vnrm_inv = vnrm_inv;
+  d->scaleS = inv_beta;
+  d->zcoef = beta_n * vnrm_inv;
   d->nrm[par ^ 1] = beta_n;
   d->active = 1;
-  const double eta_n = -s * eta;
-  const int32_t it = d->iter + 1;
   d->iter = it;
-  if (hist) hist[it - 1] = fabs(eta_n) / d->bnorm;
+  if (hist) hist[it - 1] = fabs(eta_n) / in.bnorm;
   const int q = par ^ 1;
   d->beta[q] = beta_n;
   d->c1[q] = c;
   d->s1[q] = s;
-  d->c2[q] = c1;
-  d->s2[q] = s1;
+  d->c2[q] = in.c1;
+  d->s2[q] = in.s1;
   d->eta[q] = eta_n;
-  if (fabs(eta_n) <= d->tol_abs || beta_n == 0.0) {
+  if (fabs(eta_n) <= in.tol_abs || beta_n == 0.0) {
     d->done = 1;
-  } else if (it >= d->maxit) {
+  } else if (it >= in.maxit) {
     d->done = 1;
     d->status = 1;
   }
+}
+__device__ __forceinline__ void mrs_update(mrs_dev *d, int par, double sumsq, double *hist) {
+  mrs_apply(d, par, sumsq, hist, mrs_load(d, par));
 }
 
 // One product task as the product kernels read it: a matrix layout, its

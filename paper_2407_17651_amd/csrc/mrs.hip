@@ -44,33 +44,39 @@ static inline unsigned nblk(int64_t m) { return (unsigned)std::max<int64_t>(1, c
 
 // Sum of the per-tile partials in a fixed order (deterministic): every
 // thread adds a fixed strided subset, then the wavefronts and the workgroup
-// combine in a fixed tree.
-static constexpr int SB = 1024;
+// combine in a fixed tree.  All loads (the stop flag, the recurrence state
+// and the thread's first SU partials) go out before the first result is used.
+static constexpr int SB = 256, SU = 32;
 __global__ __launch_bounds__(SB) void k_mrs_scalar(mrs_dev *d, int par, const double *__restrict__ partials,
                                                   int32_t np, double *__restrict__ hist) {
   __shared__ double red[SB / 64];
-  if (d->done) {
-    if (threadIdx.x == 0) d->active = 0;
-    return;
-  }
-  double v[8];
+  const int32_t done = d->done;
+  const mrs_in in = mrs_load(d, par);
+  double v[SU];
 #pragma unroll
-  for (int u = 0; u < 8; u++) {
+  for (int u = 0; u < SU; u++) {
     const int32_t q = (int32_t)threadIdx.x + u * SB;
     v[u] = q < np ? partials[q] : 0.0;
   }
-  for (int32_t q = threadIdx.x + 8 * SB; q < np; q += SB) v[0] += partials[q];
-  double sum = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  for (int32_t q = threadIdx.x + SU * SB; q < np; q += SB) v[0] += partials[q];
+  if (done) {
+    if (threadIdx.x == 0) d->active = 0;
+    return;
+  }
+#pragma unroll
+  for (int w = SU / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; u++) v[u] += v[u + w];
+  double sum = v[0];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
   __syncthreads();
-  if (threadIdx.x >= 64) return;
-  sum = threadIdx.x < SB / 64 ? red[threadIdx.x] : 0.0;
-#pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
   if (threadIdx.x != 0) return;
-  mrs_update(d, par, sum, hist);
+  double tot = red[0];
+#pragma unroll
+  for (int w = 1; w < SB / 64; w++) tot += red[w];
+  mrs_apply(d, par, tot, hist, in);
 }
 
 // The vector update of the last iteration when no product carried it:
