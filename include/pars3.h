@@ -107,16 +107,17 @@ typedef struct {
   int32_t bfs_levels;        /* levels of the Cuthill-McKee search (max over components) */
   int32_t engine;            /* pars3_engine in use */
   /* LDS bank passes of the product's adds (layout quality, not part of the
-   * method).  A block's entries are read in aligned halves of 32 (the two
-   * halves of a chunk); a half takes as many passes as the most frequent
-   * row offset mod 32 among its entries (row side) plus the same for the
-   * column offsets (column side).  lds_halves counts the halves of all
+   * method).  The product's FP64 LDS adds are served in quarters of a
+   * wavefront (16 lanes), so a block's entries are read in aligned runs of
+   * 16 from the block start; a run takes as many passes as the most
+   * frequent row offset mod 32 among its entries (row side) plus the same
+   * for the column offsets (column side).  lds_runs counts the runs of all
    * blocks, lds_passes_sorted sums the passes of the entries sorted by
    * (block, diagonal, row), lds_passes those of the stored order, in which
    * pars3_reorder regroups the entries of blocks where that lowers bank
    * conflicts more than it spreads the x gathers (lds_passes <=
-   * lds_passes_sorted; 2 lds_halves is the floor). */
-  int64_t lds_halves, lds_passes_sorted, lds_passes;
+   * lds_passes_sorted; 2 lds_runs is the floor). */
+  int64_t lds_runs, lds_passes_sorted, lds_passes;
 } pars3_split_info;
 
 /* Host-only validation of a strictly lower CSR (no device use).  Checks, rows

@@ -350,14 +350,14 @@ def conflict_features(L, nblocks: int = 8) -> np.ndarray:
     return f
 
 
-def lds_passes_sorted(L, tile_rows: int = 256, w_in: int = -1, t_out: int = -1):
+def lds_passes_sorted(L, tile_rows: int = 256, w_in: int = -1, t_out: int = -1, run: int = 16):
     """LDS bank passes of the product's block entries in sorted order -- a
     property of the GPU layout's bank model, not of the paper's method (pinned
     by closed forms in the tests).  The middle and outer entries of L (in the
     numbering L is given in; split as ``split``) form tile-pair blocks (row
     tile, part, column tile), each sorted by block diagonal (column offset -
     row offset mod tile_rows) and then row offset.  Each block is cut into
-    aligned runs of 32 entries; a run takes as many passes as its most
+    aligned runs of ``run`` entries; a run takes as many passes as its most
     frequent row offset mod 32 plus its most frequent column offset mod 32.
     Returns (runs, passes)."""
     n, rp, c, _ = _arrs(L)
@@ -377,11 +377,11 @@ def lds_passes_sorted(L, tile_rows: int = 256, w_in: int = -1, t_out: int = -1):
     block = np.cumsum(new_block) - 1
     first = np.flatnonzero(new_block)
     pos = np.arange(len(ri)) - first[block]
-    run = np.unique(np.stack([block, pos // 32]), axis=1, return_inverse=True)[1].ravel()
-    runs = int(run.max()) + 1
+    rid = np.unique(np.stack([block, pos // run]), axis=1, return_inverse=True)[1].ravel()
+    runs = int(rid.max()) + 1
     passes = 0
     for cls in (ri % 32, cj % 32):
-        key = run * 32 + cls
+        key = rid * 32 + cls
         cnt = np.bincount(key, minlength=runs * 32).reshape(runs, 32)
         passes += int(cnt.max(axis=1).sum())
     return runs, passes

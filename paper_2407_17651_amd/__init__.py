@@ -54,7 +54,7 @@ class SplitInfo(ctypes.Structure):
         ("nnz_inner", ctypes.c_int64), ("nnz_middle", ctypes.c_int64), ("nnz_outer", ctypes.c_int64),
         ("n_tiles", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
         ("n_components", ctypes.c_int32), ("bfs_levels", ctypes.c_int32), ("engine", ctypes.c_int32),
-        ("lds_halves", ctypes.c_int64), ("lds_passes_sorted", ctypes.c_int64), ("lds_passes", ctypes.c_int64),
+        ("lds_runs", ctypes.c_int64), ("lds_passes_sorted", ctypes.c_int64), ("lds_passes", ctypes.c_int64),
     ]
 
     def as_dict(self):

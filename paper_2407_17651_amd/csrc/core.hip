@@ -348,7 +348,7 @@ extern "C" pars3_status pars3_get_split_info(const pars3_matrix *A, pars3_split_
   info->max_blocks = L.max_blocks;
   info->n_components = A->ncomp;
   info->bfs_levels = A->nlevels;
-  info->lds_halves = L.lds_halves;
+  info->lds_runs = L.lds_runs;
   info->lds_passes_sorted = L.lds_passes_sorted;
   info->lds_passes = L.lds_passes;
   return PARS3_OK;

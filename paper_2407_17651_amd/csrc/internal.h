@@ -189,9 +189,9 @@ struct layout {
   int32_t nchunks = 0, nchunks_ovf = 0;
   // layout position of every canonical entry (-1 for inner-band entries)
   dbuf<int32_t> pos_of;
-  // LDS bank passes of the blocks' aligned halves of 32 entries (row side +
+  // LDS bank passes of the blocks' aligned runs of 16 entries (row side +
   // column side), in the sorted (diagonal) order and in the stored order
-  int64_t lds_halves = 0, lds_passes_sorted = 0, lds_passes = 0;
+  int64_t lds_runs = 0, lds_passes_sorted = 0, lds_passes = 0;
 };
 
 struct mrs_ws;

@@ -118,26 +118,28 @@ __global__ void k_block_flags(const uint64_t *__restrict__ keys, int64_t m, int 
 }
 // ---- entry order inside a block, for LDS adds without bank conflicts
 // The product adds each entry's products into the LDS row sum of its row
-// offset (row side) or column offset (column side).  A wavefront's FP64 LDS
-// add is served as two halves of 32 lanes, and two lanes of one half whose
-// offsets agree modulo 32 hit the same bank pair, for every LDS row stride the
-// kernels use (1, 3, 5 and 9 words: all odd), so such a half takes two or more
-// passes.  Chunks start at multiples of 64 entries from the block start, so
-// the halves are the aligned runs of 32 entries of a block.  The sort leaves
-// a block in diagonal order, where runs along one diagonal have distinct row
-// and column offsets; sparse diagonals mix into a half and collide.  Here each
-// half of a block is refilled as a matching between row classes (offset mod
-// 32) and column classes: entries are bucketed by (row class, column class);
-// per half, rows propose to their most loaded free column class, columns
-// accept the most loaded row class, augmenting paths complete the matching,
-// and a class is allowed a second (third, ...) entry only when no matching
-// covers the half.  Each (row, column) class pair gives its entries in
-// diagonal order and a half keeps the order of the sort.  Mixing entries from
-// all over the block spreads the x gathers of a half over more cache lines,
-// so a block keeps the new order only if it costs less (bo_cost: passes
-// against gather spread) than the sorted one: sparse, irregular blocks take
-// it, blocks of dense diagonal runs (stencils) mostly keep the sorted order.  One 64-thread workgroup per block; lanes 0-31 stand for the
-// row classes, lanes 32-63 for the column classes.
+// offset (row side) or column offset (column side).  gfx950 serves a
+// wavefront's FP64 LDS add in four quarters of 16 lanes (16 x 8 bytes), and
+// two lanes of one quarter whose offsets agree modulo 32 hit the same bank
+// pair, for every LDS row stride the kernels use (1, 3, 5 and 9 words: all
+// odd), so such a quarter takes two or more passes; lanes of different
+// quarters never conflict.  Chunks start at multiples of 64 entries from the
+// block start, so the quarters are the aligned runs of BO_RUN = 16 entries
+// of a block.  The sort leaves a block in diagonal order, where runs along
+// one diagonal have distinct row and column offsets; sparse diagonals mix
+// into a run and collide.  Here each run of a block is refilled as a
+// matching between row classes (offset mod 32) and column classes: entries
+// are bucketed by (row class, column class); per run, rows propose to their
+// most loaded free column class, columns accept the most loaded row class,
+// augmenting paths complete the matching, and a class is allowed a second
+// (third, ...) entry only when no matching covers the run.  Each (row,
+// column) class pair gives its entries in diagonal order and a run keeps the
+// order of the sort.  Mixing entries from all over the block spreads the x
+// gathers of a run over more cache lines, so a block keeps the new order
+// only if it costs less (bo_cost: passes against gather spread) than the
+// sorted one.  One 64-thread workgroup per block segment; lanes 0-31 stand
+// for the row classes, lanes 32-63 for the column classes.
+static constexpr int BO_RUN = 16;
 static constexpr int BO_NB = 32 * 32;
 
 __device__ __forceinline__ int bo_bucket(uint64_t k, int lgT) {
@@ -155,24 +157,26 @@ __device__ __forceinline__ int bo_max(int v) {
   for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
   return v;
 }
-// One half of 32 entries (entry q of lane l & 31, or q < 0 for none): its
-// LDS passes (row side + column side: the most loaded row class plus the
-// most loaded column class) and the 16-row units of x its gathers touch on
-// both sides.  Lanes 0-31 look at the row offsets (the row side's LDS slot,
-// the column side's x row), lanes 32-63 at the column offsets.
-struct bo_half {
+// One run of BO_RUN entries (entry q of lane l & 31, or q < 0 for none; lanes
+// with l & 31 >= BO_RUN pass q < 0): its LDS passes (row side + column side:
+// the most loaded row class plus the most loaded column class) and the
+// 16-row units of x its gathers touch on both sides.  Lanes 0-31 look at the
+// row offsets (the row side's LDS slot, the column side's x row), lanes
+// 32-63 at the column offsets.
+struct bo_run {
   int passes, units;
 };
 // The cost that decides between the two orders of a block: BO_PASS_WEIGHT x
 // passes + units.  The weight is a measured exchange rate: on the batched
-// 8-right-hand-side product (256 matrices), weights of 3, 5 and 10 took
-// 0.532, 0.510 and 0.494 ms per launch.
-static constexpr int BO_PASS_WEIGHT = 10;
-__device__ __forceinline__ int bo_cost(bo_half h) { return BO_PASS_WEIGHT * h.passes + h.units; }
+// 8-right-hand-side product (256 matrices), weights of 10 and 20 took 0.447
+// and 0.440 ms per launch (its 2D grids 0.100 and 0.083 ms, its 3D grids
+// 0.107 and 0.110 ms); the single-matrix products did not move.
+static constexpr int BO_PASS_WEIGHT = 20;
+__device__ __forceinline__ int bo_cost(bo_run h) { return BO_PASS_WEIGHT * h.passes + h.units; }
 // Lane src's value of v; src is the same on every lane (v_readlane).
 __device__ __forceinline__ int bo_lane(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
 
-__device__ __forceinline__ bo_half bo_half_eval(const uint64_t *__restrict__ keys, int32_t q, int lgT, int lane) {
+__device__ __forceinline__ bo_run bo_run_eval(const uint64_t *__restrict__ keys, int32_t q, int lgT, int lane) {
   const uint32_t T1 = (1u << lgT) - 1u;
   int o = -1;
   if (q >= 0) {
@@ -182,20 +186,20 @@ __device__ __forceinline__ bo_half bo_half_eval(const uint64_t *__restrict__ key
   }
   int mult = 0;
   bool first = o >= 0;
-  for (int j = 0; j < 32; j++) {
+  for (int j = 0; j < BO_RUN; j++) {
     const int lo = bo_lane(o, j), hi = bo_lane(o, 32 + j);
     const int oj = lane < 32 ? lo : hi;
     mult += (o >= 0) & (oj >= 0) & ((oj & 31) == (o & 31));
     first &= !(j < (lane & 31) && oj >= 0 && (oj >> 4) == (o >> 4));
   }
-  bo_half h;
+  bo_run h;
   h.passes = bo_max(lane < 32 ? mult : 0) + bo_max(lane < 32 ? 0 : mult);
   h.units = (int)__popcll(__ballot(first));
   return h;
 }
 
 // A block is cut into ceil(m / BO_SEG) segments of equal size (rounded up to
-// whole halves, so that every segment starts at a half boundary), each
+// whole chunk halves, so that every segment starts at a run boundary), each
 // regrouped on its own by one workgroup: a block of thousands of entries
 // (1024-row tiles, dense rows) would otherwise serialise the launch behind
 // one wavefront.  Segments of 512 entries cut the blocks of 256-row tiles of
@@ -229,16 +233,16 @@ __global__ __launch_bounds__(64) void k_bank_order(const uint64_t *__restrict__ 
   const int32_t bs = bstart[lo], be = bstart[lo + 1], nseg = segp[lo + 1] - segp[lo];
   const int32_t size = ((be - bs + nseg - 1) / nseg + 31) & ~31;
   const int32_t s = min(be, bs + (g - segp[lo]) * size), e = min(be, s + size);
-  int32_t *st = stats + 3 * (int64_t)g;  // halves, passes of the sorted order, passes kept
+  int32_t *st = stats + 3 * (int64_t)g;  // runs, passes of the sorted order, passes kept
   // the sorted order's cost
-  int32_t cost_orig = 0, pass_orig = 0, halves = 0;
-  for (int32_t h0 = s; h0 < e; h0 += 32) {
-    const bo_half hv = bo_half_eval(keys, h0 + cls < e ? h0 + cls : -1, lgT, lane);
+  int32_t cost_orig = 0, pass_orig = 0, runs = 0;
+  for (int32_t h0 = s; h0 < e; h0 += BO_RUN) {
+    const bo_run hv = bo_run_eval(keys, cls < BO_RUN && h0 + cls < e ? h0 + cls : -1, lgT, lane);
     cost_orig += bo_cost(hv);
     pass_orig += hv.passes;
-    halves++;
+    runs++;
   }
-  bool keep = halves <= 1 || pass_orig == 2 * halves;  // nothing to gain
+  bool keep = runs <= 1 || pass_orig == 2 * runs;  // nothing to gain
   int32_t pass_new = 0;
   if (!keep) {
     // bucket sizes, their starts (exclusive scan, 16 buckets per lane), and
@@ -292,8 +296,8 @@ __global__ __launch_bounds__(64) void k_bank_order(const uint64_t *__restrict__ 
     }
     int32_t cost_new = 0;
     for (int32_t out = s; out < e && !keep;) {
-      const int need = min(32, (int)(e - out));
-      int cnt = 0;  // entries of this lane's class in the half
+      const int need = min(BO_RUN, (int)(e - out));
+      int cnt = 0;  // entries of this lane's class in the run
       int got = 0;
       // a class limit of 33 admits every remaining entry, so the loop ends by then
       for (int lim = 1; got < need && lim <= 40; lim++) {
@@ -365,11 +369,20 @@ __global__ __launch_bounds__(64) void k_bank_order(const uint64_t *__restrict__ 
             c = prev;
           }
         }
-        // take the matched pairs (at most need - got, rows in ascending order)
+        // take the most loaded matched pairs (at most need - got of them:
+        // by the remaining entries of the row class plus those of its
+        // column class, ties to the lower row class), so that heavy classes
+        // are not left to pile up in the last runs
         const uint32_t mrows = (uint32_t)__ballot(isrow && mate >= 0);
         const int take = min(__popc(mrows), need - got);
         if (take == 0) continue;
-        const int slot = isrow ? __popc(mrows & ((1u << cls) - 1u)) : 0;
+        const int remc = __shfl(rem, 32 + (max(mate, 0) & 31), 64);
+        const int key = (isrow && mate >= 0) ? rem + remc : -1;
+        int slot = 0;
+        for (int r = 0; r < 32; r++) {
+          const int kr = bo_lane(key, r);
+          slot += (kr > key) | ((kr == key) & (r < cls));
+        }
         const bool use = isrow && mate >= 0 && slot < take;
         const int ru = __shfl(use ? mate : -1, max(mate, 0) & 31, 64);
         const bool col_used = !isrow && mate >= 0 && ru == cls;
@@ -393,7 +406,7 @@ __global__ __launch_bounds__(64) void k_bank_order(const uint64_t *__restrict__ 
         break;
       }
       __syncthreads();
-      const bo_half hv = bo_half_eval(keys, cls < need ? s_grp[cls] : -1, lgT, lane);
+      const bo_run hv = bo_run_eval(keys, cls < need ? s_grp[cls] : -1, lgT, lane);
       cost_new += bo_cost(hv);
       pass_new += hv.passes;
       if (cost_new >= cost_orig) keep = true;  // cannot end cheaper any more
@@ -415,7 +428,7 @@ __global__ __launch_bounds__(64) void k_bank_order(const uint64_t *__restrict__ 
     }
   }
   if (lane == 0) {
-    st[0] = halves;
+    st[0] = runs;
     st[1] = pass_orig;
     st[2] = keep ? pass_orig : pass_new;
   }
@@ -704,7 +717,7 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
   P3_HIP(hipMemcpyAsync(L.blk_start.p + nb, &m32, sizeof(int32_t), hipMemcpyHostToDevice, s));
   if (nnz > 0) P3_TRY(fill_i32(L.pos_of.p, -1, nnz, s));
   if (m > 0) {
-    // conflict-free halves inside each block: (k0, v0) -> (k1, v1)
+    // conflict-free runs inside each block: (k0, v0) -> (k1, v1)
     k_block_starts<<<nblk(m), TB, 0, s>>>(bflag.p, bpos.p, m, L.blk_start.p);
     P3_LAUNCHED();
     dbuf<int32_t> lst, bst, scnt, segp;
@@ -728,13 +741,13 @@ pars3_status split_and_layout(pars3_matrix *A, const pars3_split_params &p, hipS
     long long h3[3] = {0, 0, 0};
     P3_HIP(hipMemcpyAsync(h3, tot.p, sizeof(h3), hipMemcpyDeviceToHost, s));
     P3_HIP(hipStreamSynchronize(s));
-    L.lds_halves = h3[0];
+    L.lds_runs = h3[0];
     L.lds_passes_sorted = h3[1];
     L.lds_passes = h3[2];
     std::swap(k0.p, k1.p);
     std::swap(v0.p, v1.p);
   } else {
-    L.lds_halves = L.lds_passes_sorted = L.lds_passes = 0;
+    L.lds_runs = L.lds_passes_sorted = L.lds_passes = 0;
   }
   k1.release();
   v1.release();

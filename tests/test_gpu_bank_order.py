@@ -1,6 +1,7 @@
 """Entry order inside the layout's tile-pair blocks.  pars3_reorder regroups
-the entries of a block into aligned runs of 32 whose row offsets and column
-offsets fall into distinct LDS bank classes (offset mod 32) where that pays,
+the entries of a block into aligned runs of 16 (a quarter of a wavefront's
+LDS add) whose row offsets and column offsets fall into distinct LDS bank
+classes (offset mod 32) where that pays,
 so the product's LDS adds take fewer passes.  The split info reports the
 passes of the sorted (diagonal) order, which must equal the oracle's count
 exactly, and of the stored order, which is never worse; the products over a
@@ -31,7 +32,7 @@ def test_sorted_order_passes_match_the_oracle(name, tile_rows):
     info = p3.Matrix(L).reorder(tile_rows=tile_rows, value_dtype=p3.F32).info()
     _, B = oracle_reordered(L)
     runs, passes = oracle.lds_passes_sorted(B, tile_rows)
-    assert info["lds_halves"] == runs
+    assert info["lds_runs"] == runs
     assert info["lds_passes_sorted"] == passes
     assert 2 * runs <= info["lds_passes"] <= passes
 
@@ -45,12 +46,12 @@ def test_irregular_blocks_take_fewer_passes():
 
 
 def test_conflict_free_order_is_kept():
-    """A path graph in its own numbering: every run is 32 consecutive rows of
+    """A path graph in its own numbering: every run is 16 consecutive rows of
     one diagonal, already at the floor of 2 passes, so nothing moves."""
     n = 256 * 5
     L = synth.from_edges(n, [(i, i + 1) for i in range(n - 1)], relabel=False, seed=5)
     info = p3.Matrix(L).reorder(permute=0).info()
-    assert info["lds_passes"] == info["lds_passes_sorted"] == 2 * info["lds_halves"]
+    assert info["lds_passes"] == info["lds_passes_sorted"] == 2 * info["lds_runs"]
 
 
 @pytest.mark.parametrize("tile_rows", [64, 256, 1024])
