@@ -247,6 +247,39 @@ def evaluate(d=None, epochs: int = 400, seed: int = 7, ablations: bool = True):
     return out, mlp
 
 
+def retimed(count: int = 16, reps: int = 10, log=None) -> dict:
+    """Regret re-timed in one session, as regret is defined: for the first
+    `count` held-out matrices, the trained network selects a configuration
+    from features the library computes now (pars3_select), then
+    pars3_autotune times every configuration of the grid in the same
+    session; regret = t(selected) / t(best) - 1 over those timings (within 2%
+    counts as a tie in ``within_2pct``).  The paper's configuration is scored
+    on the same timings."""
+    import synth
+    import paper_2407_17651_amd as p3
+
+    net, grid = load_trained(p3)
+    table = grid_table(grid)
+    paper = paper_index(table)
+    specs = synth.selector_specs(N_MATRICES)
+    first = N_MATRICES - N_HELD_OUT
+    rs, rp, rows = [], [], []
+    for q in range(first, first + count):
+        L = synth.make(specs[q], "uniform_f32")
+        M = p3.Matrix(L)
+        c = p3.pars3_select(M.h, net, grid)
+        res, best = p3.pars3_autotune(M.h, grid=grid, k=1, reps=reps)
+        t = np.array([r["us"] for r in res], np.float64)
+        rs.append(t[c] / t[best] - 1.0)
+        rp.append(t[paper] / t[best] - 1.0)
+        rows.append((q, specs[q]["family"], L.n, int(c), int(best)))
+        M.close()
+        if log is not None:
+            print(f"[retimed] {q} {specs[q]['family']} n={L.n} selected={c} best={best} "
+                  f"regret={rs[-1]:.4f} paper={rp[-1]:.4f}", file=log, flush=True)
+    return {"matrices": count, "mlp": summary(rs), "paper_default": summary(rp), "rows": rows}
+
+
 def regrets_all(times_us):
     t = np.asarray(times_us, np.float64)
     best = np.where(t > 0, t, np.inf).min(1, keepdims=True)
@@ -333,6 +366,9 @@ def main(argv=None):
     e = sub.add_parser("evaluate")
     e.add_argument("--data", default=DATA)
     e.add_argument("--epochs", type=int, default=400)
+    r = sub.add_parser("retimed")
+    r.add_argument("--count", type=int, default=N_HELD_OUT)
+    r.add_argument("--reps", type=int, default=10)
     a = ap.parse_args(argv)
     root = os.path.dirname(HERE)
     if root not in sys.path:
@@ -353,6 +389,9 @@ def main(argv=None):
         out, mlp = evaluate(load(a.data), epochs=a.epochs)
         save_trained(mlp, a.out)
         print(json.dumps(out), flush=True)
+    elif a.cmd == "retimed":
+        out = retimed(a.count, a.reps, log=sys.stdout)
+        print(json.dumps({k: v for k, v in out.items() if k != "rows"}), flush=True)
     else:
         out, _ = evaluate(load(a.data), epochs=a.epochs)
         print(json.dumps(out), flush=True)

@@ -60,6 +60,18 @@ def test_saved_network_selects_well(data):
     assert r.mean() < rp.mean()
 
 
+def test_regret_retimed_in_one_session():
+    """Regret as defined: the network's choice (from features computed now)
+    and the exhaustive best, both timed in this session by pars3_autotune on
+    16 held-out matrices of the current library; the network beats the
+    paper's configuration on the same timings."""
+    out = selector.retimed(16, reps=10)
+    print("[gpu] selector retimed " + json.dumps({k: v for k, v in out.items() if k != "rows"}), flush=True)
+    assert out["matrices"] == 16
+    assert out["mlp"]["mean"] < out["paper_default"]["mean"]
+    assert out["mlp"]["within_2pct"] >= 0.5
+
+
 def _grid_tuple(g):
     return (g.w_in, g.t_out, g.tile_rows, g.value_dtype, g.keep_fp64, g.permute, g.engine)
 
