@@ -136,15 +136,15 @@ def batched(args, p3, synth, torch, np):
             M.reorder(value_dtype=p3.F32, keep_fp64=1, tile_rows=T)
         return p3.Batch(mats)
 
+    # the batch's tile height, per operation, by the library's batch-level
+    # autotuner (whole batch launches timed per height; the handles are left
+    # split with the fastest)
     tiles = (256, 512, 1024)
-    tune = {}
-    for T in tiles:
-        bat = split_all(T)
-        tune[T] = (time_launch(bat, xs, ys, 8, p3.F32, 5), time_launch(bat, ones, bs, 1, p3.F64, 5))
-        del bat
-    t8 = min(tiles, key=lambda T: tune[T][0])
-    t1 = min(tiles, key=lambda T: tune[T][1])
-    bat = split_all(t8)
+    us1, b1 = p3.pars3_batch_autotune(mats, tiles, k=1, vec_dtype=p3.F64, reps=5)
+    us8, b8 = p3.pars3_batch_autotune(mats, tiles, k=8, vec_dtype=p3.F32, reps=5)
+    tune = {T: (us8[j] * 1e-3, us1[j] * 1e-3) for j, T in enumerate(tiles)}
+    t8, t1 = tiles[b8], tiles[b1]
+    bat = p3.Batch(mats)
     reps = max(10, args.steps // 4)
     ms = time_launch(bat, xs, ys, 8, p3.F32, reps)
     nsum = sum(L.n for L in Ls)

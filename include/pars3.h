@@ -475,6 +475,27 @@ pars3_status pars3_batch_spmv(pars3_batch *B, const double *shifts, const void *
 pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alphas, const double *const *b, double *const *x,
                                    const pars3_mrs_opts *opts, pars3_mrs_info *infos, void *stream);
 
+/* Batch-level autotuner: the tile height shared by a batch, chosen by timing
+ * whole batch launches (a batch's work list is one queue per XCD over all its
+ * matrices' tiles, so the best height for the batch is not that of each
+ * matrix alone; Section 3.1.2 leaves the split to the user).  For each
+ * tile_rows[j] (64, 128, 256, 512 or 1024; nt >= 1) every reordered handle
+ * mats[0..m) is split again with that height (its reordering and other split
+ * parameters kept, engine set to PARS3_ENGINE_TILES), a batch is made over
+ * them and `reps` launches of pars3_batch_spmv with k right-hand sides of
+ * vec_dtype (fixed vectors the call allocates, zero shifts, the stored
+ * values) are timed with hipEvents on `stream` (warm-up, then the median of
+ * three runs of reps launches).  us[j] (host, nt) receives microseconds per
+ * launch, *best (may be NULL) the fastest index, and every handle is left
+ * split with that height; batches made over the handles before the call
+ * must be made again (ESTATE otherwise, as after any re-split).  Errors:
+ * EINVAL (NULL or empty arrays, a bad height, k, vec_dtype or reps), ESTATE
+ * (a handle not reordered), those of pars3_reorder and pars3_batch_spmv (the
+ * handles then stay split with the height being tried).  Synchronous. */
+pars3_status pars3_batch_autotune(pars3_matrix *const *mats, int32_t m, const int32_t *tile_rows, int32_t nt,
+                                  int32_t k, int32_t vec_dtype, int32_t reps, double *us, int32_t *best,
+                                  void *stream);
+
 /* Learned configuration selector: a multilayer perceptron
  *   x -> ReLU(x W1 + b1) -> ReLU(h1 W2 + b2) -> h2 W3 + b3
  * from the standardised features (pars3_features) of a reordered matrix to

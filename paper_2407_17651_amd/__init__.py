@@ -128,6 +128,7 @@ SIGNATURES = {
     "pars3_batch_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _vp], _st),
     "pars3_batch_spmv": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp], _st),
     "pars3_batch_mrs_solve": ([_vp, _vp, _vp, _vp, ctypes.POINTER(MrsOpts), _vp, _vp], _st),
+    "pars3_batch_autotune": ([_vp, _i32, _vp, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_i32), _vp], _st),
     "pars3_mlp_create": ([_i32, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)], _st),
     "pars3_mlp_destroy": ([_vp], None),
     "pars3_mlp_sizes": ([_vp, _vp, ctypes.POINTER(_i64)], _st),
@@ -564,6 +565,19 @@ class MLP:
         _check(lib().pars3_mlp_select_rows(self.h, _ptr(X), int(X.shape[0]), _ptr(valid), _ptr(choice),
                                            _stream(stream)), "pars3_mlp_select_rows")
         return choice
+
+
+def pars3_batch_autotune(mats, tile_rows=(256, 512, 1024), k=1, vec_dtype=F64, reps=10, stream=None):
+    """Tile height of a batch by timing whole batch launches over reordered
+    ``Matrix`` objects (left split with the fastest).  Returns (us, best):
+    microseconds per launch for each height and the index of the fastest."""
+    arr = (_vp * len(mats))(*[m.h for m in mats])
+    tr = np.ascontiguousarray(tile_rows, np.int32)
+    us = np.zeros(len(tr), np.float64)
+    best = _i32()
+    _check(lib().pars3_batch_autotune(arr, len(mats), _ptr(tr), len(tr), int(k), int(vec_dtype), int(reps), _ptr(us),
+                                      ctypes.byref(best), _stream(stream)), "pars3_batch_autotune")
+    return us, best.value
 
 
 class Batch:

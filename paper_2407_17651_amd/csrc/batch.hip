@@ -613,3 +613,107 @@ extern "C" pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alph
   if (worst == 1) return fail(PARS3_ENOCONV, "batch mrs: at least one system did not converge");
   return PARS3_OK;
 }
+
+// ------------------------------------------------------------ batch-level autotuner
+namespace p3 {
+// a fixed pattern in [-1, 1) for the timing vectors
+__global__ void k_batch_tune_fill(double *__restrict__ a, float *__restrict__ b, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint32_t h = (uint32_t)(i * 2654435761u) >> 8;
+  const double v = (double)h * (2.0 / 16777216.0) - 1.0;
+  if (a) a[i] = v;
+  if (b) b[i] = (float)v;
+}
+}  // namespace p3
+
+extern "C" pars3_status pars3_batch_autotune(pars3_matrix *const *mats, int32_t m, const int32_t *tile_rows,
+                                             int32_t nt, int32_t k, int32_t vec_dtype, int32_t reps, double *us,
+                                             int32_t *best, void *stream) {
+  using namespace p3;
+  if (!mats || m < 1 || !tile_rows || nt < 1 || !us)
+    return fail(PARS3_EINVAL, "batch autotune: NULL or empty argument");
+  if (k != 1 && k != 2 && k != 4 && k != 8) return fail(PARS3_EINVAL, "batch autotune: k must be 1, 2, 4 or 8");
+  if (vec_dtype != PARS3_F64 && vec_dtype != PARS3_F32) return fail(PARS3_EINVAL, "batch autotune: bad vec_dtype");
+  if (reps < 1) return fail(PARS3_EINVAL, "batch autotune: reps must be >= 1");
+  for (int32_t j = 0; j < nt; j++) {
+    const int32_t T = tile_rows[j];
+    if (T != 64 && T != 128 && T != 256 && T != 512 && T != 1024)
+      return fail(PARS3_EINVAL, "batch autotune: tile_rows must be 64, 128, 256, 512 or 1024 (got %d)", T);
+  }
+  for (int32_t i = 0; i < m; i++) {
+    if (!mats[i]) return fail(PARS3_EINVAL, "batch autotune: matrix %d is NULL", i);
+    if (!mats[i]->split_done) return fail(PARS3_ESTATE, "batch autotune: matrix %d is not reordered", i);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // timing vectors: matrix i's x and y at 256-byte aligned offsets
+  const size_t elem = vec_dtype == PARS3_F64 ? sizeof(double) : sizeof(float);
+  std::vector<size_t> off(m + 1, 0);
+  for (int32_t i = 0; i < m; i++) off[i + 1] = off[i] + ((size_t)mats[i]->n * k * elem + 255) / 256 * 256;
+  const int64_t total = (int64_t)std::max<size_t>(off[m] / elem, 1);
+  dbuf<char> xb, yb;
+  P3_HIP(xb.alloc(off[m] + 256));
+  P3_HIP(yb.alloc(off[m] + 256));
+  k_batch_tune_fill<<<(unsigned)cdiv(total, 256), 256, 0, s>>>(
+      vec_dtype == PARS3_F64 ? (double *)xb.p : nullptr, vec_dtype == PARS3_F32 ? (float *)xb.p : nullptr, total);
+  P3_LAUNCHED();
+  std::vector<const void *> xs(m);
+  std::vector<void *> ys(m);
+  for (int32_t i = 0; i < m; i++) {
+    xs[i] = xb.p + off[i];
+    ys[i] = yb.p + off[i];
+  }
+  hipEvent_t e0, e1;
+  P3_HIP(hipEventCreate(&e0));
+  P3_HIP(hipEventCreate(&e1));
+  pars3_status st = PARS3_OK;
+  int32_t ib = -1;
+  for (int32_t j = 0; j < nt && st == PARS3_OK; j++) {
+    us[j] = -1.0;
+    // every matrix re-split with this tile height (its reordering and other
+    // split parameters kept), then one batch over them
+    for (int32_t i = 0; i < m && st == PARS3_OK; i++) {
+      pars3_split_params p = mats[i]->params;
+      p.tile_rows = tile_rows[j];
+      p.engine = PARS3_ENGINE_TILES;
+      st = pars3_reorder(mats[i], &p, stream);
+    }
+    if (st != PARS3_OK) break;
+    pars3_batch *B = nullptr;
+    st = pars3_batch_create(m, mats, &B);
+    if (st != PARS3_OK) break;
+    // warm-up (captures the launch), then the median of three batches of
+    // reps launches
+    for (int r = 0; r < 3 && st == PARS3_OK; r++)
+      st = pars3_batch_spmv(B, nullptr, xs.data(), ys.data(), k, vec_dtype, -1, stream);
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < 3 && st == PARS3_OK; b++) {
+      if (hipEventRecord(e0, s) != hipSuccess) st = fail(PARS3_EHIP, "batch autotune: event record failed");
+      for (int r = 0; r < reps && st == PARS3_OK; r++)
+        st = pars3_batch_spmv(B, nullptr, xs.data(), ys.data(), k, vec_dtype, -1, stream);
+      if (st == PARS3_OK && hipEventRecord(e1, s) != hipSuccess)
+        st = fail(PARS3_EHIP, "batch autotune: event record failed");
+      float ms = 0.f;
+      if (st == PARS3_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(PARS3_EHIP, "batch autotune: event timing failed");
+      t[b] = 1e3 * (double)ms / reps;
+    }
+    pars3_batch_destroy(B);
+    if (st != PARS3_OK) break;
+    std::sort(t, t + 3);
+    us[j] = t[1];
+    if (ib < 0 || us[j] < us[ib]) ib = j;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != PARS3_OK) return st;
+  // leave every matrix split with the fastest tile height
+  for (int32_t i = 0; i < m; i++) {
+    pars3_split_params p = mats[i]->params;
+    p.tile_rows = tile_rows[ib];
+    p.engine = PARS3_ENGINE_TILES;
+    P3_TRY(pars3_reorder(mats[i], &p, stream));
+  }
+  if (best) *best = ib;
+  return PARS3_OK;
+}

@@ -302,3 +302,51 @@ def test_batched_mrs_nan_system_reports_enan():
     for i in (0, 1, 3):
         assert infos[i]["status"] == 0
         assert oracle.residual(Ls[i], alphas[i], bh[i], xs[i].cpu().numpy()) <= 1e-10
+
+
+@pytest.mark.parametrize("k,value_dtype", [(8, p3.F32), (1, p3.F64)])
+def test_batch_autotune_leaves_the_fastest_height(k, value_dtype):
+    """pars3_batch_autotune times whole batch launches per tile height, leaves
+    every handle split with the fastest, and a batch made then multiplies as
+    the oracle does."""
+    specs, Ls = mixed_set(10, 91 + k)
+    print(f"[gpu] batch autotune k={k} dtype={value_dtype}", flush=True)
+    mats = reordered(Ls, value_dtype, tiles=256)
+    heights = (128, 256, 512)
+    vec = p3.F64 if value_dtype == p3.F64 else p3.F32
+    us, best = p3.pars3_batch_autotune(mats, heights, k=k, vec_dtype=vec, reps=5)
+    assert us.shape == (3,) and np.all(us > 0) and best == int(np.argmin(us))
+    for M in mats:
+        assert M.info()["tile_rows"] == heights[best]
+        assert M.info()["value_dtype"] == value_dtype
+    bat = p3.Batch(mats)
+    tdt = torch.float64 if vec == p3.F64 else torch.float32
+    Xs = [synth.vector(L.n, 300 + i, k) if k > 1 else synth.vector(L.n, 300 + i) for i, L in enumerate(Ls)]
+    xs = [to_dev(X, tdt) for X in Xs]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    shifts = np.array([s["alpha"] for s in specs])
+    bat.spmv(xs, ys, shifts, k=k, vec_dtype=vec)
+    torch.cuda.synchronize()
+    tol = 1e-12 if vec == p3.F64 else 1e-5
+    for i, L in enumerate(Ls):
+        got = ys[i].double().cpu().numpy()
+        assert rel_inf(got, oracle_product(L, shifts[i], Xs[i], vec)) <= tol
+
+
+def test_batch_autotune_errors():
+    Ls = [synth.grid2d(30, 1), synth.grid2d(20, 2)]
+    mats = [p3.Matrix(L).reorder() for L in Ls]
+    for kw in (dict(tile_rows=(100,)), dict(k=3), dict(vec_dtype=p3.BF16), dict(reps=0), dict(tile_rows=())):
+        with pytest.raises(p3.Pars3Error) as e:
+            p3.pars3_batch_autotune(mats, **kw)
+        assert e.value.status == p3.EINVAL, kw
+    with pytest.raises(p3.Pars3Error) as e:
+        p3.pars3_batch_autotune(mats + [p3.Matrix(synth.grid2d(10, 3))])
+    assert e.value.status == p3.ESTATE
+    # a batch made before the call sees the re-split (another tile height)
+    bat = p3.Batch(mats)
+    p3.pars3_batch_autotune(mats, (128,), reps=1)
+    x = [torch.zeros(L.n, dtype=torch.float64, device="cuda") for L in Ls]
+    with pytest.raises(p3.Pars3Error) as e:
+        bat.spmv(x, [torch.empty_like(v) for v in x])
+    assert e.value.status == p3.ESTATE
