@@ -74,13 +74,27 @@ def measured_traffic(dtype, tile_rows=256, w_in=0):
         return None
 
 
+SETTLE_MS = 30.0  # untimed busy time before the warm-up steps of every leg
+
+
 def timed_steps(fn, copies, warmup, steps, torch):
     """Average milliseconds per call of fn(s) over `steps` timed calls.  Every
     rotation copy is used once first (its first use may run one-time work
-    such as a library's analysis), then `warmup` untimed calls, then the
-    timed ones between two HIP events on the current stream."""
+    such as a library's analysis); then untimed calls for SETTLE_MS of wall
+    time, since the GPU reaches its steady clock only after some
+    milliseconds of continuous work (200 products right after a few warm-up
+    calls measured 29.8 us per step, then 28.3 and 28.0 in the next two runs
+    of 200); then `warmup` untimed calls, then the timed ones between two
+    HIP events on the current stream."""
     for c in range(copies):
         fn(c)
+    torch.cuda.synchronize()
+    t0, s = time.perf_counter(), 0
+    while (time.perf_counter() - t0) * 1e3 < SETTLE_MS:
+        for _ in range(copies):
+            fn(s)
+            s += 1
+        torch.cuda.synchronize()
     for s in range(warmup):
         fn(s)
     torch.cuda.synchronize()
