@@ -304,9 +304,42 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
 
 // Output phase of a tile (after its LDS row sums are complete): y = (shift
 // + d_i) x + inner band + LDS sum (+ the solver epilogue), one store per row.
-template <class V, class X, int K, bool EP, bool GEN>
-__device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const X (&xown)[K], const double *ys,
-                                           double *s_red) {
+// What the solver epilogue reads besides the row sums: for the thread's first
+// own row the vectors, and two of the iteration's coefficients.  In a
+// single-matrix product they are requested when the tile starts, so their
+// latency passes while the tile's gathers run instead of adding one more
+// memory round trip after them (mixed-precision solves 4-11% faster).  The
+// batched product requests them at the end: there the early loads made the
+// batched solve 2% slower.  (The five update coefficients are read at the end
+// in both: held from the start they would take the scalar registers of one
+// wavefront per SIMD.)
+template <class X>
+struct ep_pre {
+  X sc = (X)1, zb = (X)0;
+  bool upd = false;
+  X z = (X)0, p1 = (X)0, p2 = (X)0, xs = (X)0;
+};
+
+template <class X, int K>
+__device__ __forceinline__ void ep_load(const prod_task &a, int64_t row, ep_pre<X> &e) {
+  if (a.scale) e.sc = (X)glb(a.scale)[0];
+  if (a.z) {
+    e.zb = (X)glb(a.beta)[0];
+    if constexpr (K == 1) e.z = glb((const X *)a.z)[row];
+  }
+  if (K == 1 && a.vec) {
+    // the rows are read whether or not the update is due (the buffers exist
+    // for every solver task); only their use depends on the active flag
+    e.upd = glb(a.active)[0] != 0;
+    e.p1 = glb((const X *)a.p1)[row];
+    e.p2 = glb((const X *)a.p2)[row];
+    e.xs = glb((const X *)a.xs)[row];
+  }
+}
+
+template <class V, class X, int K, bool EP, bool GEN, bool PF>
+__device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const X (&xown)[K], const ep_pre<X> &ep,
+                                           const double *ys, double *s_red) {
   gptr<V> dia = glb((const V *)a.dia);
   gptr<X> x = glb((const X *)a.x);
   gmut<X> y = glbw((X *)a.y);
@@ -318,20 +351,20 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
   const int32_t r0 = t << a.lgT;
   const int32_t rows = min(1 << a.lgT, n - r0);
   // fused solver iteration: scale of S x, and the pending vector update
-  X sc = (X)1;
-  bool upd = false;
+  X sc = ep.sc;
+  bool upd = K == 1 && a.vec && ep.upd;
+  if constexpr (EP && !PF) {
+    sc = a.scale ? (X)glb(a.scale)[0] : (X)1;
+    upd = K == 1 && a.vec && glb(a.active)[0];
+  }
   double vd = 0.0, ve = 0.0, vg = 1.0, vc = 0.0, vn = 0.0;
-  if constexpr (EP) {
-    if (a.scale) sc = (X)glb(a.scale)[0];
-    if (K == 1 && a.vec && glb(a.active)[0]) {
-      gptr<double> vec = glb(a.vec);
-      upd = true;
-      vd = vec[0];
-      ve = vec[1];
-      vg = vec[2];
-      vc = vec[3];
-      vn = vec[4];
-    }
+  if (EP && upd) {
+    gptr<double> vec = glb(a.vec);
+    vd = vec[0];
+    ve = vec[1];
+    vg = vec[2];
+    vc = vec[3];
+    vn = vec[4];
   }
   double sq = 0.0;
   for (int32_t r = threadIdx.x, rr = 0; r < rows; r += TB, rr++) {
@@ -379,16 +412,23 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
       acc[c] = EP ? sh * xi + sc * acc[c] : sh * xi + acc[c];
     }
     if (EP && z) {
-      const X zb = (X)glb(a.beta)[0];
+      const X zb = PF ? ep.zb : (X)glb(a.beta)[0];
+      if constexpr (K == 1) {
+        const X zi = PF && rr == 0 ? ep.z : z[i];
+        acc[0] += zb * zi;
+        if (upd) {
+          gmut<X> p2 = glbw((X *)a.p2);
+          gmut<X> xs = glbw((X *)a.xs);
+          gptr<X> p1 = glb((const X *)a.p1);
+          const X p1i = PF && rr == 0 ? ep.p1 : p1[i], p2i = PF && rr == 0 ? ep.p2 : p2[i];
+          const X xsi = PF && rr == 0 ? ep.xs : xs[i];
+          const double pn = ((double)zi * vn - vd * (double)p1i - ve * (double)p2i) / vg;
+          p2[i] = (X)pn;
+          xs[i] = (X)((double)xsi + vc * pn);
+        }
+      } else {
 #pragma unroll
-      for (int c = 0; c < K; c++) acc[c] += zb * z[i * K + c];
-      if (upd) {
-        gmut<X> p2 = glbw((X *)a.p2);
-        gmut<X> xs = glbw((X *)a.xs);
-        gptr<X> p1 = glb((const X *)a.p1);
-        const double pn = ((double)z[i] * vn - vd * (double)p1[i] - ve * (double)p2[i]) / vg;
-        p2[i] = (X)pn;
-        xs[i] = (X)((double)xs[i] + vc * pn);
+        for (int c = 0; c < K; c++) acc[c] += zb * z[i * K + c];
       }
     }
     rowvec<X, K>::store(y, i, acc);
@@ -422,7 +462,7 @@ __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const 
 // GEN: the task's kind (symmetric or skew) and diagonal array are honoured;
 // without it the product is the skew one with the scalar shift only.  E:
 // the type of the entry words (uint16_t for tiles of at most 256 rows).
-template <class V, class X, int K, bool EP, bool GEN, class E>
+template <class V, class X, int K, bool EP, bool GEN, class E, bool PF>
 __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double *ys, double *s_red) {
   gptr<V> ent_v = glb((const V *)a.ent_v);
   gptr<E> ent_rc = glb((const E *)a.ent_rc);
@@ -446,6 +486,8 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
   // value it never uses) so that no branch surrounds the load
   X xown[K];
   rowvec<X, K>::load(x, min((int64_t)r0 + threadIdx.x, (int64_t)n - 1), xown);
+  ep_pre<X> ep;
+  if constexpr (EP && PF) ep_load<X, K>(a, min((int64_t)r0 + threadIdx.x, (int64_t)n - 1), ep);
   for (int32_t s = threadIdx.x; s < rows * KP<K>; s += TB) ys[s] = 0.0;
   __syncthreads();
   if constexpr (K < 8) {
@@ -470,7 +512,7 @@ __device__ __forceinline__ void tile_body(const prod_task &a, int32_t t, double 
     chunk_group<V, X, K, E>(d, lane, lgT, GEN && a.sym != 0, ent_rc, ent_v, x, ys);
   }
   __syncthreads();
-  tile_final<V, X, K, EP, GEN>(a, t, xown, ys, s_red);
+  tile_final<V, X, K, EP, GEN, PF>(a, t, xown, ep, ys, s_red);
 }
 
 // One matrix: one workgroup per tile.  EP: with the solver epilogue (a
@@ -485,7 +527,7 @@ __global__ __launch_bounds__(TB) void k_tile_product(const prod_task a) {
   if (EP && a.done && glb(a.done)[0] && !(a.active && glb(a.active)[0])) return;
   const int32_t t = xcd_tile(blockIdx.x, a.ntiles);
   if (t >= a.ntiles) return;
-  tile_body<V, X, K, EP, GEN, E>(a, t, ys, s_red);
+  tile_body<V, X, K, EP, GEN, E, EP>(a, t, ys, s_red);
 }
 
 
@@ -512,12 +554,12 @@ __global__ __launch_bounds__(TB) void k_batch_product(const prod_task *__restric
   const prod_task &a = tasks[w.x];
   if (EP && a.done && glb(a.done)[0] && !(a.active && glb(a.active)[0])) return;
   if constexpr (EW == 2) {
-    tile_body<V, X, K, EP, GEN, uint16_t>(a, w.y, ys, s_red);
+    tile_body<V, X, K, EP, GEN, uint16_t, false>(a, w.y, ys, s_red);
   } else if constexpr (EW == 4) {
-    tile_body<V, X, K, EP, GEN, uint32_t>(a, w.y, ys, s_red);
+    tile_body<V, X, K, EP, GEN, uint32_t, false>(a, w.y, ys, s_red);
   } else {
-    if (a.lgT <= ENT16_MAX_LGT) tile_body<V, X, K, EP, GEN, uint16_t>(a, w.y, ys, s_red);
-    else tile_body<V, X, K, EP, GEN, uint32_t>(a, w.y, ys, s_red);
+    if (a.lgT <= ENT16_MAX_LGT) tile_body<V, X, K, EP, GEN, uint16_t, false>(a, w.y, ys, s_red);
+    else tile_body<V, X, K, EP, GEN, uint32_t, false>(a, w.y, ys, s_red);
   }
 }
 
