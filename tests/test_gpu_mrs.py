@@ -119,6 +119,31 @@ def test_repeated_solves_and_new_splits(precision):
         prev = (tiles, info, x)
 
 
+@pytest.mark.parametrize("precision", [p3.F64, p3.F32, p3.BF16])
+def test_tall_tiles_match_oracle_history(precision):
+    """1024-row tiles: every thread writes four rows of its tile, and only
+    the first of them has its epilogue vectors requested when the tile
+    starts.  The FP64 solve's residual history and iterate stay within 1e-8
+    of the oracle's over its first 60 iterations; every precision meets the
+    FP64 residual bound."""
+    L = synth.rgg2d(30000, 12.0, 8)
+    alpha = 0.3
+    b = oracle.spmv(L, alpha, np.ones(L.n))
+    keep = int(precision != p3.F64)
+    print(f"[gpu] mrs 1024-row tiles precision={precision} n={L.n}", flush=True)
+    M = p3.Matrix(L).reorder(value_dtype=precision, keep_fp64=keep, tile_rows=1024)
+    assert M.info()["tile_rows"] == 1024
+    if precision == p3.F64:
+        st, info, hist, x = solve(M, alpha, b, hist_len=60, tol=0.0, maxit=60)
+        xo, io, ho = oracle.mrs(L, alpha, b, tol=0.0, maxit=60)
+        assert st == p3.ENOCONV and info["iters"] == io["iters"] == 60
+        assert np.all(np.abs(hist - ho) <= 1e-8 * ho + 1e-300), np.max(np.abs(hist - ho) / ho)
+        assert rel_inf(x, xo) <= 1e-8
+    st, info, _, x = solve(M, alpha, b, tol=1e-10, maxit=20000, precision=precision)
+    assert st == p3.OK, info
+    assert oracle.residual(L, alpha, b, x) <= 1e-10
+
+
 def test_workload1_fp64_and_mixed():
     """3D 128^3 stencil with N(0,1) values, alpha = 0.5, b = A 1, to 1e-10."""
     L = synth.workload(1)
