@@ -302,13 +302,12 @@ __device__ __forceinline__ void chunk_group(const uint2 (&d)[PRE], int32_t lane,
   }
 }
 
-// Output phase of a tile (after its LDS row sums are complete): y = (shift
-// + d_i) x + inner band + LDS sum (+ the solver epilogue), one store per row.
 // What the solver epilogue reads besides the row sums: for the thread's first
 // own row the vectors, and two of the iteration's coefficients.  In a
 // single-matrix product they are requested when the tile starts, so their
 // latency passes while the tile's gathers run instead of adding one more
-// memory round trip after them (mixed-precision solves 4-11% faster).  The
+// memory round trip after them (MRS to 1e-10 on a 2M-row stencil: 2.5%
+// faster in FP64 and with FP32 inner solves, 8.5% with BF16 ones).  The
 // batched product requests them at the end: there the early loads made the
 // batched solve 2% slower.  (The five update coefficients are read at the end
 // in both: held from the start they would take the scalar registers of one
@@ -337,6 +336,10 @@ __device__ __forceinline__ void ep_load(const prod_task &a, int64_t row, ep_pre<
   }
 }
 
+// Output phase of a tile (after its LDS row sums are complete): y = (shift
+// + d_i) x + inner band + LDS sum (+ the solver epilogue), one store per row.
+// PF: the epilogue's first-row vectors and coefficients were requested when
+// the tile started (ep); otherwise they are read here.
 template <class V, class X, int K, bool EP, bool GEN, bool PF>
 __device__ __forceinline__ void tile_final(const prod_task &a, int32_t t, const X (&xown)[K], const ep_pre<X> &ep,
                                            const double *ys, double *s_red) {
