@@ -484,8 +484,8 @@ pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alphas, const d
  * parameters kept, engine set to PARS3_ENGINE_TILES), a batch is made over
  * them and `reps` launches of pars3_batch_spmv with k right-hand sides of
  * vec_dtype (fixed vectors the call allocates, zero shifts, the stored
- * values) are timed with hipEvents on `stream` (warm-up, then the median of
- * three runs of reps launches).  us[j] (host, nt) receives microseconds per
+ * values) are timed with hipEvents on `stream` (at least 20 ms of warm-up
+ * launches, then the median of three runs of reps launches).  us[j] (host, nt) receives microseconds per
  * launch, *best (may be NULL) the fastest index, and every handle is left
  * split with that height; batches made over the handles before the call
  * must be made again (ESTATE otherwise, as after any re-split).  Errors:

@@ -684,10 +684,18 @@ extern "C" pars3_status pars3_batch_autotune(pars3_matrix *const *mats, int32_t 
     pars3_batch *B = nullptr;
     st = pars3_batch_create(m, mats, &B);
     if (st != PARS3_OK) break;
-    // warm-up (captures the launch), then the median of three batches of
+    // warm-up: launches for at least 20 ms of wall time (the first captures
+    // the launch; the GPU reaches its steady clock only after some
+    // milliseconds of continuous work), then the median of three batches of
     // reps launches
-    for (int r = 0; r < 3 && st == PARS3_OK; r++)
+    const auto w0 = std::chrono::steady_clock::now();
+    for (int r = 0; st == PARS3_OK; r++) {
       st = pars3_batch_spmv(B, nullptr, xs.data(), ys.data(), k, vec_dtype, -1, stream);
+      if (st == PARS3_OK && (r & 3) == 3) {
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(PARS3_EHIP, "batch autotune: sync failed");
+        if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count() >= 20.0) break;
+      }
+    }
     double t[3] = {0.0, 0.0, 0.0};
     for (int b = 0; b < 3 && st == PARS3_OK; b++) {
       if (hipEventRecord(e0, s) != hipSuccess) st = fail(PARS3_EHIP, "batch autotune: event record failed");
