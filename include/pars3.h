@@ -334,7 +334,9 @@ void pars3_csr_destroy(pars3_csr *C);
  * reordering is computed once and kept; t_out = -1 and -2 are resolved against
  * beta, and t_out is raised to w_in where it would fall below it), times
  * pars3_spmv-equivalent products with k right-hand sides on a fixed vector
- * (median of three batches of reps products, hipEvents on `stream`), writes
+ * (median of three batches of reps products, hipEvents on `stream`, after
+ * 3 warm-up products, and before the first configuration products for at
+ * least 20 ms so that the GPU clock is steady), writes
  * out[g] = {resolved parameters, microseconds per product}, sets *best (may
  * be NULL) to the fastest index and leaves A split with that configuration.
  * Synchronous.  Timings are of cache-warm repeated products. */
@@ -485,8 +487,9 @@ pars3_status pars3_batch_mrs_solve(pars3_batch *B, const double *alphas, const d
  * them and `reps` launches of pars3_batch_spmv with k right-hand sides of
  * vec_dtype (fixed vectors the call allocates, zero shifts, the stored
  * values) are timed with hipEvents on `stream` (at least 20 ms of warm-up
- * launches, then the median of three runs of reps launches).  us[j] (host, nt) receives microseconds per
- * launch, *best (may be NULL) the fastest index, and every handle is left
+ * launches, then the median of three runs of reps launches).  us[j] (host,
+ * nt) receives microseconds per launch, *best (may be NULL) the fastest
+ * index, and every handle is left
  * split with that height; batches made over the handles before the call
  * must be made again (ESTATE otherwise, as after any re-split).  Errors:
  * EINVAL (NULL or empty arrays, a bad height, k, vec_dtype or reps), ESTATE

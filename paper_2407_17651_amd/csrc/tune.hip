@@ -7,6 +7,7 @@
 // configuration is applied again at the end.  The table of timings is the
 // training record of the learned selector.
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <vector>
 
@@ -116,8 +117,20 @@ extern "C" pars3_status pars3_autotune(pars3_matrix *A, const pars3_split_params
     const int vec = p.value_dtype == PARS3_F64 ? PARS3_F64 : PARS3_F32;
     const void *x = vec == PARS3_F64 ? (const void *)x64.p : (const void *)x32.p;
     void *y = vec == PARS3_F64 ? (void *)y64.p : (void *)y32.p;
-    // warm-up, then the median of three batches of reps products
-    for (int r = 0; r < 3 && st == PARS3_OK; r++) st = spmv_rcm(A, 0.5, x, y, k, vec, s);
+    // warm-up (before the first configuration, products for at least 20 ms
+    // of wall time: the GPU reaches its steady clock only after some
+    // milliseconds of continuous work; the re-splits between configurations
+    // keep it busy), then the median of three batches of reps products
+    const auto w0 = std::chrono::steady_clock::now();
+    for (int r = 0; st == PARS3_OK; r++) {
+      st = spmv_rcm(A, 0.5, x, y, k, vec, s);
+      if (st != PARS3_OK || r < 2) continue;
+      if (g > 0) break;
+      if ((r & 7) == 7) {
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(PARS3_EHIP, "autotune: sync failed");
+        if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count() >= 20.0) break;
+      }
+    }
     double t[3];
     for (int b = 0; b < 3 && st == PARS3_OK; b++) {
       if (hipEventRecord(e0, s) != hipSuccess) st = fail(PARS3_EHIP, "autotune: event record failed");
